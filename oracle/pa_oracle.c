@@ -1,0 +1,222 @@
+/* FP64 CPU oracle: plain loops, no blocking, no fusion.
+ * TEST INFRASTRUCTURE ONLY -- see pa_oracle.h.  Never linked into the product.
+ */
+#include "pa_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int geom_ok(const or_geom* g) {
+  if (!g) return 0;
+  if (g->ndim != 2 && g->ndim != 3) return 0;
+  if (g->nx < 0 || g->ny < 0 || g->nz < 0) return 0;
+  if (g->ndim == 2 && g->nz != 1) return 0;
+  if (g->n_sensors < 0 || g->n_samples < 0) return 0;
+  if (!(g->h > 0) || !(g->dt > 0) || !(g->c > 0) || !(g->r_min >= 0)) return 0;
+  if (g->n_sensors > 0 && !g->sensors) return 0;
+  return 1;
+}
+
+static int64_t npix(const or_geom* g) { return (int64_t)g->nx * g->ny * g->nz; }
+
+static double rmin_of(const or_geom* g) { return g->r_min > 0 ? g->r_min : 0.5 * g->h; }
+
+/* pixel centre: center + (i - (n-1)/2) h on each axis */
+static void pixel_pos(const or_geom* g, int64_t p, double r[3]) {
+  int64_t ix = p % g->nx;
+  int64_t iy = (p / g->nx) % g->ny;
+  int64_t iz = p / ((int64_t)g->nx * g->ny);
+  r[0] = g->center[0] + ((double)ix - 0.5 * (g->nx - 1)) * g->h;
+  r[1] = g->center[1] + ((double)iy - 0.5 * (g->ny - 1)) * g->h;
+  r[2] = g->center[2] + ((double)iz - 0.5 * (g->nz - 1)) * g->h;
+}
+
+/* distance R_ps (clamped) between pixel p and sensor s */
+static double dist(const or_geom* g, int64_t p, int32_t s) {
+  double r[3];
+  pixel_pos(g, p, r);
+  const double* q = g->sensors + (int64_t)s * g->ndim;
+  double d2 = 0.0;
+  for (int a = 0; a < g->ndim; ++a) d2 += (r[a] - q[a]) * (r[a] - q[a]);
+  double R = sqrt(d2);
+  double rm = rmin_of(g);
+  return R > rm ? R : rm;
+}
+
+/* delay of an arrival in sample units */
+static double delay(const or_geom* g, double R) { return (R / g->c - g->t0) / g->dt; }
+
+static double hat(double u) {
+  double a = 1.0 - fabs(u);
+  return a > 0.0 ? a : 0.0;
+}
+
+static void set_threads(int threads) {
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#else
+  (void)threads;
+#endif
+}
+
+int or_forward(const or_geom* g, const double* x, double* y, int threads) {
+  if (!geom_ok(g)) return -1;
+  const int32_t S = g->n_sensors, K = g->n_samples;
+  const int64_t P = npix(g);
+  set_threads(threads);
+  /* each sensor row is owned by one thread: fixed summation order over p */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t s = 0; s < S; ++s) {
+    double* row = y + (int64_t)s * K;
+    for (int32_t k = 0; k < K; ++k) row[k] = 0.0;
+    for (int64_t p = 0; p < P; ++p) {
+      double R = dist(g, p, s);
+      double tau = delay(g, R);
+      double k0d = floor(tau);
+      double f = tau - k0d;
+      double w = 1.0 / R;
+      if (k0d >= 0.0 && k0d <= (double)(K - 1)) row[(int64_t)k0d] += w * (1.0 - f) * x[p];
+      if (k0d + 1.0 >= 0.0 && k0d + 1.0 <= (double)(K - 1)) row[(int64_t)k0d + 1] += w * f * x[p];
+    }
+  }
+  return 0;
+}
+
+int or_adjoint(const or_geom* g, const double* y, double* x, int threads) {
+  if (!geom_ok(g)) return -1;
+  const int32_t S = g->n_sensors, K = g->n_samples;
+  const int64_t P = npix(g);
+  set_threads(threads);
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < P; ++p) {
+    double acc = 0.0;
+    for (int32_t s = 0; s < S; ++s) {
+      const double* row = y + (int64_t)s * K;
+      double R = dist(g, p, s);
+      double tau = delay(g, R);
+      double k0d = floor(tau);
+      double f = tau - k0d;
+      double w = 1.0 / R;
+      if (k0d >= 0.0 && k0d <= (double)(K - 1)) acc += w * (1.0 - f) * row[(int64_t)k0d];
+      if (k0d + 1.0 >= 0.0 && k0d + 1.0 <= (double)(K - 1)) acc += w * f * row[(int64_t)k0d + 1];
+    }
+    x[p] = acc;
+  }
+  return 0;
+}
+
+double or_forward_at(const or_geom* g, const double* x, int32_t s, int32_t k) {
+  if (!geom_ok(g) || s < 0 || s >= g->n_sensors || k < 0 || k >= g->n_samples) return NAN;
+  const int64_t P = npix(g);
+  double acc = 0.0;
+  for (int64_t p = 0; p < P; ++p) {
+    double R = dist(g, p, s);
+    acc += x[p] * hat((double)k - delay(g, R)) / R;
+  }
+  return acc;
+}
+
+double or_adjoint_at(const or_geom* g, const double* y, int64_t p) {
+  if (!geom_ok(g) || p < 0 || p >= npix(g)) return NAN;
+  double acc = 0.0;
+  for (int32_t s = 0; s < g->n_sensors; ++s) {
+    double R = dist(g, p, s);
+    double tau = delay(g, R);
+    for (int32_t k = 0; k < g->n_samples; ++k)
+      acc += hat((double)k - tau) / R * y[(int64_t)s * g->n_samples + k];
+  }
+  return acc;
+}
+
+static double dot(const double* a, const double* b, int64_t n) {
+  double acc = 0.0;
+  for (int64_t i = 0; i < n; ++i) acc += a[i] * b[i];
+  return acc;
+}
+
+/* CGLS (Hestenes-Stiefel CG on the shifted normal equations, Bjorck's form):
+ *   r = y - A x;  s = A^T r - lambda x;  p = s;  gamma = ||s||^2
+ *   repeat: q = A p;  delta = ||q||^2 + lambda ||p||^2;  alpha = gamma / delta
+ *           x += alpha p;  r -= alpha q;  s = A^T r - lambda x
+ *           gamma' = ||s||^2;  beta = gamma' / gamma;  p = s + beta p
+ * It minimises F(x) = ||A x - y||^2 + lambda ||x||^2; s = -grad F / 2. */
+int or_cgls(const or_geom* g, const double* y, double* x, int iters, double lambda,
+            int x0_zero, double* hist, int threads) {
+  if (!geom_ok(g) || iters < 0 || !(lambda >= 0)) return -1;
+  const int64_t P = npix(g);
+  const int64_t M = (int64_t)g->n_sensors * g->n_samples;
+  double* r = (double*)malloc(sizeof(double) * (M ? M : 1));
+  double* q = (double*)malloc(sizeof(double) * (M ? M : 1));
+  double* s = (double*)malloc(sizeof(double) * (P ? P : 1));
+  double* p = (double*)malloc(sizeof(double) * (P ? P : 1));
+  if (!r || !q || !s || !p) { free(r); free(q); free(s); free(p); return -1; }
+
+  if (x0_zero) memset(x, 0, sizeof(double) * P);
+  or_forward(g, x, q, threads);
+  for (int64_t i = 0; i < M; ++i) r[i] = y[i] - q[i];
+  or_adjoint(g, r, s, threads);
+  for (int64_t i = 0; i < P; ++i) s[i] -= lambda * x[i];
+  memcpy(p, s, sizeof(double) * P);
+  double gamma = dot(s, s, P);
+  if (hist) {
+    double rr = dot(r, r, M);
+    hist[0] = sqrt(rr);
+    hist[1] = sqrt(gamma);
+    hist[2] = rr + lambda * dot(x, x, P);
+  }
+  int stop = iters;
+  for (int k = 0; k < iters; ++k) {
+    or_forward(g, p, q, threads);
+    double delta = dot(q, q, M) + lambda * dot(p, p, P);
+    if (gamma == 0.0 || delta == 0.0 || !isfinite(delta) || !isfinite(gamma)) {
+      stop = k;
+      if (hist)
+        for (int j = k + 1; j <= iters; ++j) memcpy(hist + 3 * j, hist + 3 * k, 3 * sizeof(double));
+      break;
+    }
+    double alpha = gamma / delta;
+    for (int64_t i = 0; i < P; ++i) x[i] += alpha * p[i];
+    for (int64_t i = 0; i < M; ++i) r[i] -= alpha * q[i];
+    or_adjoint(g, r, s, threads);
+    for (int64_t i = 0; i < P; ++i) s[i] -= lambda * x[i];
+    double gamma1 = dot(s, s, P);
+    double beta = gamma1 / gamma;
+    gamma = gamma1;
+    for (int64_t i = 0; i < P; ++i) p[i] = s[i] + beta * p[i];
+    if (hist) {
+      double rr = dot(r, r, M);
+      hist[3 * (k + 1) + 0] = sqrt(rr);
+      hist[3 * (k + 1) + 1] = sqrt(gamma);
+      hist[3 * (k + 1) + 2] = rr + lambda * dot(x, x, P);
+    }
+  }
+  free(r); free(q); free(s); free(p);
+  return stop;
+}
+
+/* Landweber / gradient iteration on the same objective with a fixed step:
+ * x <- x + omega * (A^T (y - A x) - lambda x), i.e. x <- x - (omega/2) grad F. */
+int or_landweber(const or_geom* g, const double* y, double* x, int iters, double lambda,
+                 double omega, double* hist, int threads) {
+  if (!geom_ok(g) || iters < 0 || !(lambda >= 0)) return -1;
+  const int64_t P = npix(g);
+  const int64_t M = (int64_t)g->n_sensors * g->n_samples;
+  double* r = (double*)malloc(sizeof(double) * (M ? M : 1));
+  double* s = (double*)malloc(sizeof(double) * (P ? P : 1));
+  if (!r || !s) { free(r); free(s); return -1; }
+  memset(x, 0, sizeof(double) * P);
+  for (int k = 0; k <= iters; ++k) {
+    or_forward(g, x, r, threads);
+    for (int64_t i = 0; i < M; ++i) r[i] = y[i] - r[i];
+    if (hist) hist[k] = dot(r, r, M) + lambda * dot(x, x, P);
+    if (k == iters) break;
+    or_adjoint(g, r, s, threads);
+    for (int64_t i = 0; i < P; ++i) x[i] += omega * (s[i] - lambda * x[i]);
+  }
+  free(r); free(s);
+  return 0;
+}

@@ -1,0 +1,276 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these re-derives the oracle's own loops: they check hand-worked
+arrivals (tests/golden), exact invariants of linear interpolation, the
+adjoint identity, geometric symmetry, and the textbook solutions that CGLS
+and Landweber must reach on tiny dense problems.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import Geometry, ring_sensors, fibonacci_hemisphere, segment_phantom
+from golden_cases import load_point_sources
+
+
+def small_geom(ndim=2, n=12, S=8, K=96, h=2e-4, radius=4e-3, dt=None, t0=0.0, nz=None):
+    if ndim == 2:
+        sens = ring_sensors(S, radius)
+        nzz = 1
+    else:
+        sens = fibonacci_hemisphere(S, radius)
+        nzz = n if nz is None else nz
+    if dt is None:
+        # all arrivals inside the trace: max distance / (c * (K - 3))
+        half = math.sqrt(ndim) * (n - 1) * h / 2
+        dt = (radius + half) / (1500.0 * (K - 3))
+    return Geometry(ndim, n, n, nzz, h, (0.0, 0.0, 0.0), sens, K, dt, t0)
+
+
+def pixel_positions(g):
+    ix = np.arange(g.nx) - (g.nx - 1) / 2
+    iy = np.arange(g.ny) - (g.ny - 1) / 2
+    iz = np.arange(g.nz) - (g.nz - 1) / 2
+    Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+    pos = np.stack([X.ravel() * g.h + g.center[0], Y.ravel() * g.h + g.center[1],
+                    Z.ravel() * g.h + g.center[2]], 1)
+    return pos[:, : g.ndim]
+
+
+def distances(g):
+    P = pixel_positions(g)
+    d = np.sqrt(((P[:, None, :] - g.sensors[None, :, :]) ** 2).sum(-1))
+    rmin = g.r_min if g.r_min > 0 else g.h / 2
+    return np.maximum(d, rmin)           # [P][S]
+
+
+# --------------------------------------------------------------------------
+# hand-worked arrivals (closed form)
+
+@pytest.mark.parametrize("case", load_point_sources(), ids=lambda c: c["name"])
+def test_point_source_golden(case):
+    g = case["geom"]
+    x = np.zeros(g.n_pixels)
+    x[case["pixel"]] = 1.0
+    y = oracle.forward(g, x.reshape(g.image_shape))
+    expect = np.zeros(g.n_samples)
+    for k, v in case["taps"].items():
+        expect[k] = v
+    np.testing.assert_allclose(y[0], expect, rtol=1e-13, atol=1e-13 * max(expect.max(), 1))
+    # the adjoint of a unit sample returns the same weight at that pixel
+    for k, v in case["taps"].items():
+        e = np.zeros(g.data_shape)
+        e[0, k] = 1.0
+        xa = oracle.adjoint(g, e).reshape(-1)
+        assert xa[case["pixel"]] == pytest.approx(v, rel=1e-13)
+        if g.n_pixels == 1:
+            assert np.count_nonzero(xa) == 1
+
+
+# --------------------------------------------------------------------------
+# invariants
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_zeroth_and_first_moment(ndim):
+    """With both taps inside the trace, sum_k y = sum_p x/R and sum_k k y = sum_p x tau/R."""
+    g = small_geom(ndim, n=10 if ndim == 2 else 6, S=6, K=80)
+    rng = np.random.default_rng(7)
+    x = rng.uniform(0, 1, size=g.image_shape)
+    y = oracle.forward(g, x)
+    R = distances(g)
+    tau = (R / g.c - g.t0) / g.dt
+    assert tau.min() > 0 and tau.max() < g.n_samples - 1
+    xf = x.reshape(-1)
+    m0 = (xf[:, None] / R).sum(0)
+    m1 = (xf[:, None] * tau / R).sum(0)
+    k = np.arange(g.n_samples)
+    np.testing.assert_allclose(y.sum(1), m0, rtol=1e-12)
+    np.testing.assert_allclose((y * k).sum(1), m1, rtol=1e-12)
+
+
+def test_adjoint_of_unit_trace_is_inverse_distance():
+    g = small_geom(2, n=9, S=5, K=64)
+    R = distances(g)
+    for s in range(g.n_sensors):
+        y = np.zeros(g.data_shape)
+        y[s, :] = 1.0
+        x = oracle.adjoint(g, y).reshape(-1)
+        np.testing.assert_allclose(x, 1.0 / R[:, s], rtol=1e-13)
+
+
+@pytest.mark.parametrize("ndim,t0", [(2, 0.0), (2, 3.7e-7), (3, -2e-7)])
+def test_adjoint_identity(ndim, t0):
+    g = small_geom(ndim, n=14 if ndim == 2 else 7, S=9, K=70, t0=t0)
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=g.image_shape)
+    y = rng.normal(size=g.data_shape)
+    lhs = float((oracle.forward(g, x) * y).sum())
+    rhs = float((x * oracle.adjoint(g, y)).sum())
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + abs(rhs))
+
+
+def test_dense_brute_force_transpose_and_hat_definition():
+    """A built column by column equals (A^T built row by row)^T, and every entry
+    equals the direct hat-function evaluation (taps leaving the trace included)."""
+    g = small_geom(2, n=6, S=4, K=40)
+    g = g.replace(dt=g.dt * 0.8)         # push some late arrivals past the trace end
+    P, M = g.n_pixels, g.n_sensors * g.n_samples
+    A = np.zeros((M, P))
+    for p in range(P):
+        e = np.zeros(P)
+        e[p] = 1.0
+        A[:, p] = oracle.forward(g, e.reshape(g.image_shape)).reshape(-1)
+    At = np.zeros((P, M))
+    for m in range(M):
+        e = np.zeros(M)
+        e[m] = 1.0
+        At[:, m] = oracle.adjoint(g, e.reshape(g.data_shape)).reshape(-1)
+    assert np.array_equal(A, At.T)
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=P)
+    y = A @ x
+    for m in range(0, M, 7):
+        s, k = divmod(m, g.n_samples)
+        assert oracle.forward_at(g, x, s, k) == pytest.approx(y[m], rel=1e-12, abs=1e-9)
+    r = rng.normal(size=M)
+    xa = At @ r
+    for p in range(P):
+        assert oracle.adjoint_at(g, r, p) == pytest.approx(xa[p], rel=1e-12, abs=1e-9)
+    # some energy really was dropped past the end of the trace
+    R = distances(g)
+    assert ((R / g.c - g.t0) / g.dt).max() > g.n_samples - 1
+
+
+def test_rotation_by_quarter_turn_shifts_sensors():
+    """Ring of S = 0 mod 4 sensors around a square centred grid: rotating the
+    image by +90 degrees rotates every arrival to the sensor S/4 further on."""
+    g = small_geom(2, n=16, S=12, K=90)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(size=g.image_shape)
+    xr = x[::-1, :].T                       # x'(X, Y) = x(Y, -X): +90 degrees about the centre
+    y = oracle.forward(g, x)
+    yr = oracle.forward(g, xr)
+    np.testing.assert_allclose(yr, np.roll(y, g.n_sensors // 4, axis=0), rtol=1e-9, atol=1e-9 * np.abs(y).max())
+
+
+def test_time_origin_shift():
+    g = small_geom(2, n=10, S=5, K=100)
+    m = 7
+    g = g.replace(dt=g.dt * 1.3)          # leave the last m+1 samples of every trace empty
+    rng = np.random.default_rng(9)
+    x = rng.uniform(size=g.image_shape)
+    y = oracle.forward(g, x)
+    assert np.all(y[:, -m - 1:] == 0)
+    ys = oracle.forward(g.replace(t0=g.t0 - m * g.dt), x)
+    np.testing.assert_allclose(ys[:, m:], y[:, :-m], rtol=1e-9, atol=1e-10 * np.abs(y).max())
+    assert np.all(ys[:, :m] == 0)
+
+
+def test_empty_and_degenerate_shapes():
+    g = small_geom(2, n=4, S=3, K=16)
+    g0 = g.replace(sensors=np.zeros((0, 2)))
+    assert oracle.forward(g0, np.ones(g.image_shape)).shape == (0, 16)
+    np.testing.assert_array_equal(oracle.adjoint(g0, np.zeros((0, 16))), 0)
+    gk = g.replace(n_samples=0)
+    assert oracle.forward(gk, np.ones(g.image_shape)).shape == (3, 0)
+    np.testing.assert_array_equal(oracle.adjoint(gk, np.zeros((3, 0))), 0)
+    gp = g.replace(nx=0)
+    assert oracle.adjoint(gp, np.ones((3, 16))).size == 0
+    np.testing.assert_array_equal(oracle.forward(gp, np.zeros((4, 0))), 0)
+
+
+# --------------------------------------------------------------------------
+# solvers against textbook solutions on tiny dense problems
+
+def dense(g):
+    P = g.n_pixels
+    A = np.zeros((g.n_sensors * g.n_samples, P))
+    for p in range(P):
+        e = np.zeros(P)
+        e[p] = 1.0
+        A[:, p] = oracle.forward(g, e.reshape(g.image_shape)).reshape(-1)
+    return A
+
+
+def tiny_problem(seed=0):
+    g = small_geom(2, n=6, S=5, K=40)
+    rng = np.random.default_rng(seed)
+    x_true = rng.uniform(size=g.image_shape)
+    y = oracle.forward(g, x_true) + 0.01 * rng.normal(size=g.data_shape)
+    return g, y
+
+
+@pytest.mark.parametrize("lam_rel", [1e-2, 1e-1])
+def test_cgls_reaches_regularised_normal_equations(lam_rel):
+    g, y = tiny_problem(1)
+    A = dense(g)
+    lam = lam_rel * np.linalg.norm(A, 2) ** 2
+    x_ref = np.linalg.solve(A.T @ A + lam * np.eye(A.shape[1]), A.T @ y.reshape(-1))
+    x, hist, stop = oracle.cgls(g, y, 3 * A.shape[1], lam)
+    assert stop == 3 * A.shape[1] or hist[stop, 1] < 1e-10 * hist[0, 1]
+    np.testing.assert_allclose(x.reshape(-1), x_ref, rtol=1e-8, atol=1e-8 * np.abs(x_ref).max())
+
+
+def krylov_minimiser(M, b, k):
+    """argmin over span{b, Mb, ..., M^(k-1) b} of x'Mx - 2 b'x (Arnoldi basis, twice re-orthogonalised)."""
+    n = b.size
+    V = np.zeros((n, k))
+    v = b / np.linalg.norm(b)
+    for j in range(k):
+        for _ in range(2):
+            v = v - V[:, :j] @ (V[:, :j].T @ v)
+        v = v / np.linalg.norm(v)
+        V[:, j] = v
+        v = M @ v
+    c = np.linalg.solve(V.T @ M @ V, V.T @ b)
+    return V @ c
+
+
+def test_cgls_iterates_minimise_over_krylov_spaces():
+    g, y = tiny_problem(2)
+    A = dense(g)
+    lam = 1e-2 * np.linalg.norm(A, 2) ** 2
+    M = A.T @ A + lam * np.eye(A.shape[1])
+    b = A.T @ y.reshape(-1)
+    prevF = np.inf
+    for k in range(1, 7):
+        x, hist, _ = oracle.cgls(g, y, k, lam)
+        xk = krylov_minimiser(M, b, k)
+        np.testing.assert_allclose(x.reshape(-1), xk, rtol=1e-7, atol=1e-7 * np.abs(xk).max())
+        F = np.sum((A @ x.reshape(-1) - y.reshape(-1)) ** 2) + lam * np.sum(x ** 2)
+        assert hist[k, 2] == pytest.approx(F, rel=1e-10)
+        assert hist[k, 0] == pytest.approx(np.linalg.norm(y.reshape(-1) - A @ x.reshape(-1)), rel=1e-9)
+        assert hist[k, 1] == pytest.approx(np.linalg.norm(A.T @ (y.reshape(-1) - A @ x.reshape(-1)) - lam * x.reshape(-1)), rel=1e-7)
+        assert F <= prevF * (1 + 1e-12)
+        prevF = F
+
+
+def test_cgls_warm_start_and_breakdown():
+    g, y = tiny_problem(3)
+    # y = 0 with x0 = 0: gamma_0 = 0, stops at iteration 0 with x = 0
+    x, hist, stop = oracle.cgls(g, np.zeros(g.data_shape), 5, 1e-3)
+    assert stop == 0 and np.all(x == 0) and np.all(hist == 0)
+    # warm start from the exact solution of a well-posed problem stays there
+    A = dense(g)
+    lam = 1e-1 * np.linalg.norm(A, 2) ** 2
+    x_ref = np.linalg.solve(A.T @ A + lam * np.eye(A.shape[1]), A.T @ y.reshape(-1))
+    x, hist, stop = oracle.cgls(g, y, 3, lam, x0=x_ref.reshape(g.image_shape))
+    np.testing.assert_allclose(x.reshape(-1), x_ref, rtol=1e-8, atol=1e-10 * np.abs(x_ref).max())
+    assert hist[0, 1] < 1e-8 * np.linalg.norm(A.T @ y.reshape(-1))
+
+
+def test_landweber_closed_form():
+    g, y = tiny_problem(4)
+    A = dense(g)
+    lam = 1e-2 * np.linalg.norm(A, 2) ** 2
+    M = A.T @ A + lam * np.eye(A.shape[1])
+    b = A.T @ y.reshape(-1)
+    omega = 1.0 / (np.linalg.norm(A, 2) ** 2 + lam)
+    k = 9
+    x, hist = oracle.landweber(g, y, k, lam, omega)
+    T = np.eye(M.shape[0]) - omega * M
+    x_ref = sum(np.linalg.matrix_power(T, j) @ (omega * b) for j in range(k))
+    np.testing.assert_allclose(x.reshape(-1), x_ref, rtol=1e-10, atol=1e-12 * np.abs(x_ref).max())
+    assert np.all(np.diff(hist) <= 1e-12 * hist[0])
