@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark: CGLS iterations/s (and A+A^T applies/s) on the 512x512 workload.
+
+One step = one full CGLS solve on the GPU: r0 = y, s0 = A^T y, p0 = s0, then
+50 iterations of (A p, ||q||^2, alpha, r update, A^T r with the x / s update,
+||s||^2, beta, p update), captured once as a HIP graph and replayed.  Inputs
+(y, geometry) are resident in HBM before timing starts.  The operator
+throughputs (A, A^T and the A+A^T pair that one iteration contains) are timed
+separately with HIP events on the same stream.
+
+Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "A+A^T applies/s and CGLS iters/s, 512²×256 sensors; rel-L2 vs FP64 oracle"
+WORKLOAD = ("512x512 image (0.05 mm pixels), ring of 256 sensors at 16 mm, 2048 samples at dt=12.5 ns, "
+            "c=1500 m/s, 200-segment vessel tree, 1% noise, lambda=1e-3, 50 CGLS iterations, "
+            "FP32 bulk with FP64 reductions")
+
+# Algorithmic FP32 work of one (pixel, sensor) pair of the plain definition:
+# difference vector (2), squared distance (3), clamp (1), sqrt (1),
+# reciprocal (1), delay (2), floor and fraction (2), two weighted taps and the
+# accumulation (6).  A fused multiply-add counts 2.
+FLOP_PER_PAIR_2D = 18
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 FLOP per FMA, without packed FP32
+# (the build disables packed FP32 instructions).
+PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--op-reps", type=int, default=50, help="launches per operator timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=4, help="oracle CGLS iterations timed on the host")
+    ap.add_argument("--quick", action="store_true", help="skip operator and CPU legs (profiling runs)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2404_10928_amd.ops as pa
+    from synth import add_noise, make_config
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda")
+    w = make_config("C2")
+    g = w.geom
+    geom = pa.DeviceGeometry(g, dev)
+    P, S, K = g.n_pixels, g.n_sensors, g.n_samples
+    pairs = P * S
+
+    # synthetic data: y = A x_true + 1% noise, generated on the GPU path itself
+    x_true = torch.from_numpy(w.x_true.astype(np.float32)).to(dev)
+    y_clean = pa.forward(x_true, geom)
+    torch.cuda.synchronize()
+    y_np = add_noise(y_clean.double().cpu().numpy(), w.noise_rel, w.noise_seeds[0])
+    y = torch.from_numpy(y_np.astype(np.float32)).to(dev)
+    torch.cuda.synchronize()
+    print(f"[bench] workload ready: P={P} S={S} K={K}", file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------ CGLS steps
+    solver = pa.CglsSolver(geom, torch.float32, w.iters, w.lam, graph=True, device=dev)
+    x = torch.empty(g.image_shape, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        solver.solve(y, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(y, x)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    iters_per_s = w.iters * args.steps / (t1 - t0)
+    hist_gpu = solver.history.cpu().numpy()
+    print(f"[bench] CGLS: {ms_per_step:.3f} ms per {w.iters}-iteration solve, {iters_per_s:.1f} it/s",
+          file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": iters_per_s, "unit": "CGLS iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded vessel-tree phantom, y = A x + 1% Gaussian noise)",
+        "config": {"workload": WORKLOAD, "image": [512, 512], "sensors": S, "samples": K,
+                   "cgls_iterations": w.iters, "step": "one full CGLS solve (graph replay)"},
+    }
+
+    if not args.quick:
+        # -------------------------------------------------- operator timings
+        stream = torch.cuda.current_stream(dev)
+        xs = torch.rand(g.image_shape, dtype=torch.float32, device=dev)
+        ys = torch.randn(g.data_shape, dtype=torch.float32, device=dev)
+        yo = torch.empty_like(ys)
+        xo = torch.empty_like(xs)
+
+        def timed(fn, reps):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps * 1e-3   # seconds per call
+
+        op = pa.Operator(geom, torch.float32, dev)
+        t_fwd = timed(lambda: op.forward_(xs, yo), args.op_reps)
+        t_adj = timed(lambda: op.adjoint_(ys, xo), args.op_reps)
+        t_pair = timed(lambda: (op.forward_(xs, yo), op.adjoint_(yo, xo)), args.op_reps)
+        out.update({
+            "a_applies_per_s": 1.0 / t_fwd, "at_applies_per_s": 1.0 / t_adj,
+            "a_plus_at_applies_per_s": 1.0 / t_pair,
+            "us_per_apply": {"A": t_fwd * 1e6, "AT": t_adj * 1e6, "A+AT": t_pair * 1e6},
+            "pairs_per_s": {"A": pairs / t_fwd, "AT": pairs / t_adj},
+        })
+        # The dominant kernel of a CGLS iteration: the slower of the two operators.
+        # The forward call includes a small zero-fill of y (1 launch, 2 MiB); the
+        # adjoint call is a single kernel.
+        dom, t_dom = ("A (fp_kernel, scatter)", t_fwd) if t_fwd > t_adj else ("A^T (bp_kernel, gather)", t_adj)
+        achieved = pairs * FLOP_PER_PAIR_2D / t_dom / 1e12
+        out["roofline"] = {
+            "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+            "work_per_launch": f"{pairs} pixel-sensor pairs x {FLOP_PER_PAIR_2D} FLOP",
+        }
+        print(f"[bench] A {t_fwd*1e6:.1f} us, A^T {t_adj*1e6:.1f} us, A+A^T {t_pair*1e6:.1f} us",
+              file=sys.stderr, flush=True)
+
+        # ------------------------------------------ parity of this run's applies
+        if not args.no_cpu_baseline:
+            import oracle
+            threads = min(16, os.cpu_count() or 1)
+            xs64 = xs.double().cpu().numpy()
+            ys64 = ys.double().cpu().numpy()
+            op.forward_(xs, yo)
+            op.adjoint_(ys, xo)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            yref = oracle.forward(g, xs64, threads=threads)
+            tb = time.perf_counter()
+            xref = oracle.adjoint(g, ys64, threads=threads)
+            tc = time.perf_counter()
+            e_a = float(np.linalg.norm(yo.double().cpu().numpy() - yref) / np.linalg.norm(yref))
+            e_at = float(np.linalg.norm(xo.double().cpu().numpy() - xref) / np.linalg.norm(xref))
+            # the oracle's own CGLS on the same y (FP64 value of the FP32 data), a bounded sample
+            it = args.cpu_iters
+            td = time.perf_counter()
+            _, hist_ref, _ = oracle.cgls(g, y.double().cpu().numpy(), it, w.lam, threads=threads)
+            te = time.perf_counter()
+            eF = float(np.max(np.abs(hist_gpu[: it + 1, 2] / hist_ref[:, 2] - 1)))
+            eR = float(np.max(np.abs(hist_gpu[: it + 1, 0] / hist_ref[:, 0] - 1)))
+            out["rel_l2_vs_fp64_oracle"] = {"A": e_a, "AT": e_at,
+                                            f"cgls_F_k_max_rel_k<={it}": eF, f"cgls_r_k_max_rel_k<={it}": eR}
+            out["cpu_baseline"] = {
+                "value": it / (te - td), "unit": "CGLS iterations/s", "cores": threads, "kind": "oracle",
+                "sample": f"FP64 C oracle CGLS, {it} iterations of the same 512x512x256x2048 problem "
+                          f"({te - td:.1f} s); A apply {tb - ta:.2f} s, A^T apply {tc - tb:.2f} s",
+                "a_plus_at_applies_per_s": 1.0 / ((tb - ta) + (tc - tb)),
+            }
+            print(f"[bench] parity A {e_a:.2e} A^T {e_at:.2e}; oracle {it} its in {te - td:.1f} s",
+                  file=sys.stderr, flush=True)
+
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

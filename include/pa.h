@@ -1,0 +1,134 @@
+/* pa.h -- matrix-free photoacoustic forward operator, its adjoint and a
+ * regularised least-squares (CGLS) solve, on one AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the paper's time-domain measurement matrix (Sec. "Principle
+ * of Iterative Reconstruction", Eq. 6: measurements y = K theta, rows indexed
+ * by (probe m, sample s), columns by pixel (i,j), entries a delta at the
+ * arrival time |r_ij - r_m| / c) with the 1/R spreading of the Green's
+ * function in Eq. 7 and a unit-peak linear hat standing for the delta on the
+ * sample grid:
+ *
+ *   R_ps   = max(|r_p - r_s|, r_min)
+ *   tau_ps = (R_ps / c - t0) / dt                       delay in samples
+ *   (A x)[s,k]   = sum_p x_p * max(0, 1 - |k - tau_ps|) / R_ps,   k = 0..K-1
+ *   (A^T y)[p]   = sum_s sum_k y[s,k] * max(0, 1 - |k - tau_ps|) / R_ps
+ *
+ * Taps falling outside 0..K-1 are dropped in both, so A^T is the exact
+ * adjoint of A.  The solve minimises ||A x - y||^2 + lambda ||x||^2, the data
+ * term of the paper's objective (Eq. 8) with a Tikhonov term, whose gradient
+ * 2 A^T (A x - y) is the statement that takes 96.7 % of the paper's runtime
+ * (Table 3).
+ *
+ * Conventions shared by every call
+ *  - Units are SI: metres, seconds, metres per second.
+ *  - Pixel (ix, iy, iz) sits at center + (i - (n - 1) / 2) * h on each axis.
+ *  - Images are [nz][ny][nx] with ix fastest (nz = 1 in 2D); measurements are
+ *    [S][K] with k fastest.  Both are dense and contiguous.
+ *  - Device pointers are the caller's (e.g. torch tensors): the library never
+ *    frees them.  They must be 16-byte aligned.  Inputs and outputs must not
+ *    overlap.
+ *  - Calls are asynchronous on the given HIP stream (NULL = the null stream):
+ *    they return once the work is enqueued; results are valid after the
+ *    caller synchronises that stream.  Outputs are overwritten, never
+ *    accumulated into.
+ *  - Argument and geometry errors are found on the host before anything is
+ *    enqueued and need no GPU.  A failing call returns a non-zero status and
+ *    leaves a message for pa_last_error(); it has enqueued nothing unless the
+ *    status is PA_ERR_HIP.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PA_ABI_VERSION 1
+
+typedef enum {
+  PA_OK = 0,
+  PA_ERR_INVALID_ARGUMENT = 1, /* null/misaligned pointer, bad size, non-finite or non-positive parameter */
+  PA_ERR_UNSUPPORTED = 2,      /* valid but outside what the kernels handle (e.g. a trace window too long for LDS) */
+  PA_ERR_WORKSPACE = 3,        /* workspace missing or smaller than pa_cgls_workspace_bytes() */
+  PA_ERR_HIP = 4,              /* a HIP runtime call failed; pa_last_error() has its message */
+  PA_ERR_BREAKDOWN = 5         /* CGLS stopped early: gamma == 0 (converged) or delta == 0 / non-finite */
+} pa_status;
+
+typedef enum {
+  PA_F32 = 0, /* x, y and the CGLS vectors are float; every inner product, norm, step size and the history are double on the GPU */
+  PA_F64 = 1  /* everything is double */
+} pa_dtype;
+
+typedef struct {
+  int32_t ndim;            /* 2 or 3 */
+  int32_t nx, ny, nz;      /* image size; nz must be 1 when ndim == 2; each >= 0 */
+  double h;                /* pixel pitch [m], > 0 */
+  double center[3];        /* position of the grid centre [m]; center[2] ignored in 2D */
+  int32_t n_sensors;       /* S >= 0 */
+  const double* sensors;   /* DEVICE pointer, [S][ndim] sensor positions [m]; may be NULL when S == 0 */
+  int32_t n_samples;       /* K >= 0 */
+  double dt;               /* sample interval [s], > 0 */
+  double t0;               /* time of sample 0 [s] (sample k is at t0 + k dt) */
+  double c;                /* speed of sound [m/s], > 0 */
+  double r_min;            /* distance clamp [m], >= 0; 0 selects h / 2 */
+} pa_geometry;
+
+/* Flags for pa_cgls_solve. */
+#define PA_X0_ZERO 1u   /* start from x0 = 0 and ignore the contents of x on entry */
+#define PA_USE_GRAPH 2u /* enqueue the whole solve as one HIP graph (captured once per argument set, then replayed) */
+
+/* Host-only check of a geometry: sizes, finiteness, and that the kernels can
+ * tile it.  Touches no GPU state and dereferences no device pointer. */
+pa_status pa_validate_geometry(const pa_geometry* g, pa_dtype dtype);
+
+/* y := A x.  x: image (float for PA_F32, double for PA_F64); y: [S][K] of the
+ * same type.  The time-domain operator of Eq. 6 as stated above. */
+pa_status pa_forward(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* hip_stream);
+
+/* x := A^T y, delay-and-interpolate back-projection: the exact adjoint of
+ * pa_forward (the K^T products of Table 4). */
+pa_status pa_adjoint(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, void* hip_stream);
+
+/* Device workspace (bytes) that pa_cgls_solve needs for this geometry, dtype
+ * and iteration count.  0 means the arguments are invalid (see pa_last_error). */
+size_t pa_cgls_workspace_bytes(const pa_geometry* g, pa_dtype dtype, int32_t iters);
+
+/* CGLS on min ||A x - y||^2 + lambda ||x||^2 (the iterative reconstruction
+ * loop of Table 3; Bjorck's CGLS form of CG on the shifted normal equations):
+ *   r = y - A x0; s = A^T r - lambda x0; p = s; gamma = ||s||^2
+ *   repeat iters times: q = A p; delta = ||q||^2 + lambda ||p||^2;
+ *     alpha = gamma / delta; x += alpha p; r -= alpha q;
+ *     s = A^T r - lambda x; beta = ||s||^2 / gamma; gamma = ||s||^2; p = s + beta p
+ * y: [S][K] device; x: image, device, in = x0 (unless PA_X0_ZERO), out = x_iters.
+ * lambda >= 0.  iters >= 0.  workspace: device, >= pa_cgls_workspace_bytes(),
+ * 256-byte aligned, owned by the caller and reused freely between calls that
+ * are not in flight at the same time.
+ * history: device double [iters + 1][3] holding (||r_k||, ||s_k||,
+ * ||r_k||^2 + lambda ||x_k||^2) per iteration, or NULL.
+ * The step sizes are computed on the GPU, so nothing is copied to the host
+ * during the solve.  If gamma or delta becomes 0 or non-finite at iteration k
+ * the remaining steps leave x unchanged; pa_cgls_stop_iteration reports k. */
+pa_status pa_cgls_solve(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, int32_t iters,
+                        double lambda, uint32_t flags, void* workspace, size_t workspace_bytes,
+                        double* history, void* hip_stream);
+
+/* After the solve's stream has been synchronised: *stop_iter = the iteration
+ * at which CGLS stopped early, or -1 if it ran all iterations.  Returns PA_OK,
+ * PA_ERR_BREAKDOWN when it stopped early, or an error.  Performs one blocking
+ * device-to-host copy. */
+pa_status pa_cgls_stop_iteration(const void* workspace, int32_t* stop_iter);
+
+/* Message for the last failing call on this thread ("" if none).  Valid until
+ * the next pa_* call on the same thread. */
+const char* pa_last_error(void);
+
+/* PA_ABI_VERSION of the loaded library. */
+int32_t pa_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PA_H */

@@ -1,0 +1,64 @@
+"""Compiles the HIP library (libpa_mi355x.so) for gfx950 with hipcc.
+
+Sources: csrc/pa_plan.cpp (host planning), csrc/pa_ops.hip (operator
+kernels), csrc/pa_blas.hip (solver kernels), csrc/pa_api.hip (C ABI).  Objects go to _build/ at the repository root; the
+shared library lands next to this file so it travels with the package.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libpa_mi355x.so")
+BUILD = os.path.join(ROOT, "_build")
+
+SOURCES = ["pa_plan.cpp", "pa_ops.hip", "pa_blas.hip", "pa_api.hip"]
+# The operator kernels never test for NaN; running them with the IEEE mode bit
+# off lets min/max skip the NaN-quieting of LDS-loaded operands.  The solver
+# kernels keep IEEE mode because they detect non-finite step sizes.
+EXTRA = {"pa_ops.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"]}
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-ffp-contract=off",              # every fused multiply-add is written out explicitly
+    "-munsafe-fp-atomics",            # hardware float atomics (LDS and global)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-pass-failed",
+    "-I", INCLUDE, "-I", CSRC,
+]
+
+
+def _compile(src: str) -> str:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{res.stdout}\n{res.stderr}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    """Always recompiles; returns the path of the shared library."""
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(_compile, SOURCES))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

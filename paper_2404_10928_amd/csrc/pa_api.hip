@@ -1,0 +1,309 @@
+// The C ABI (include/pa.h): argument checks on the host, then kernel enqueues
+// on the caller's stream.  The library allocates no device memory: the
+// caller owns every buffer, including the CGLS workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <string>
+
+#include "pa.h"
+#include "pa_kernels.h"
+#include "pa_plan.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pa_status set_err(pa_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+pa_status hip_err(hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return set_err(PA_ERR_HIP, m);
+}
+
+#define PA_HIP(call, where)                       \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_err(e_, where); \
+  } while (0)
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+pa_status plan_or_fail(const pa_geometry* g, pa_dtype dt, pa::Plan* pl) {
+  std::string msg;
+  pa_status st = pa::make_plan(g, dt, pl, &msg);
+  if (st != PA_OK) return set_err(st, msg);
+  return PA_OK;
+}
+
+pa_status check_vec(const void* p, int64_t n, size_t elem, const char* name) {
+  if (n > 0 && !p) return set_err(PA_ERR_INVALID_ARGUMENT, std::string(name) + " is NULL");
+  if (p && !aligned(p, elem)) return set_err(PA_ERR_INVALID_ARGUMENT, std::string(name) + " is not aligned to its element size");
+  return PA_OK;
+}
+
+// ---------------------------------------------------------------- CGLS enqueue
+
+struct Solve {
+  const pa::Plan* pl;
+  pa::CglsLayout L;
+  const void* y;
+  void* x;
+  int iters;
+  double lambda;
+  uint32_t flags;
+  unsigned char* ws;
+  double* hist;
+};
+
+hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
+  const pa::Plan& pl = *S.pl;
+  const pa::CglsLayout& L = S.L;
+  const pa_dtype dt = pl.dtype;
+  unsigned char* ws = S.ws;
+  int* status = reinterpret_cast<int*>(ws + L.status);
+  double* gamma = reinterpret_cast<double*>(ws + L.gamma);
+  double* alpha = reinterpret_cast<double*>(ws + L.alpha);
+  double* part_q = reinterpret_cast<double*>(ws + L.part_q);
+  double* part_r = reinterpret_cast<double*>(ws + L.part_r);
+  double* part_s = reinterpret_cast<double*>(ws + L.part_s);
+  double* part_x = reinterpret_cast<double*>(ws + L.part_x);
+  double* part_p = reinterpret_cast<double*>(ws + L.part_p);
+  void* r = ws + L.vec_r;
+  void* q = ws + L.vec_q;
+  void* s = ws + L.vec_s;
+  void* p = ws + L.vec_p;
+  hipError_t e;
+  const int gbp = std::max(pl.bp_grid, 1);
+
+  // r0 = y - A x0 ; s0 = A^T r0 - lambda x0 ; p0 = s0
+  if (S.flags & PA_X0_ZERO) {
+    if ((e = pa::launch_fill(dt, S.x, pl.P, st)) != hipSuccess) return e;
+    if ((e = pa::launch_init_r(dt, r, S.y, nullptr, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
+  } else {
+    if ((e = pa::launch_fill(dt, q, pl.M, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward_accumulate(pl, S.x, q, st)) != hipSuccess) return e;
+    if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
+  }
+  pa::CgArgs cg{S.x, p, alpha, S.lambda, part_s, part_x};
+  auto adjoint_cg = [&](const double* a) -> hipError_t {
+    if (pl.bp_grid == 0) {  // no pixels: nothing to update, the sums are zero
+      hipError_t ee = pa::launch_fill(PA_F64, part_s, gbp, st);
+      if (ee != hipSuccess) return ee;
+      return pa::launch_fill(PA_F64, part_x, gbp, st);
+    }
+    pa::CgArgs c2 = cg;
+    c2.alpha = a;
+    return pa::launch_adjoint(pl, r, s, &c2, st);
+  };
+  if ((e = adjoint_cg(alpha)) != hipSuccess) return e;
+  if ((e = pa::launch_dir(dt, p, s, pl.P, q, pl.M, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma, -1,
+                          status, S.hist, part_p, st)) != hipSuccess)
+    return e;
+  for (int k = 0; k < S.iters; ++k) {
+    if ((e = pa::launch_forward_accumulate(pl, p, q, st)) != hipSuccess) return e;
+    if ((e = pa::launch_norm2(dt, q, pl.M, part_q, st)) != hipSuccess) return e;
+    if ((e = pa::launch_upd_r(dt, r, q, pl.M, part_q, L.g_m, part_p, L.g_p, S.lambda, gamma + k, alpha + k + 1, status,
+                              k, part_r, st)) != hipSuccess)
+      return e;
+    if ((e = adjoint_cg(alpha + k + 1)) != hipSuccess) return e;
+    if ((e = pa::launch_dir(dt, p, s, pl.P, q, pl.M, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma, k,
+                            status, S.hist, part_p, st)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------ graph cache
+
+struct GraphKey {
+  pa_geometry g;
+  pa_dtype dt;
+  const void* y;
+  void* x;
+  int iters;
+  double lambda;
+  uint32_t flags;
+  void* ws;
+  double* hist;
+  int device;
+  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
+
+std::mutex g_graph_mu;
+std::list<GraphEntry>* g_graphs = nullptr;  // never destroyed: graphs live until process exit
+constexpr size_t kMaxGraphs = 16;
+hipStream_t g_capture_stream[64] = {};
+
+hipError_t get_graph(const GraphKey& key, const Solve& S, hipGraphExec_t* out) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  if (!g_graphs) g_graphs = new std::list<GraphEntry>();
+  for (auto it = g_graphs->begin(); it != g_graphs->end(); ++it) {
+    if (it->key == key) {
+      g_graphs->splice(g_graphs->begin(), *g_graphs, it);
+      *out = g_graphs->front().exec;
+      return hipSuccess;
+    }
+  }
+  hipError_t e;
+  if (key.device < 0 || key.device >= 64) return hipErrorInvalidDevice;
+  hipStream_t& cs = g_capture_stream[key.device];
+  if (!cs && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  hipError_t ee = enqueue_cgls(S, cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  if (ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return ee;
+  }
+  if (e != hipSuccess) return e;
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  if (g_graphs->size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(g_graphs->back().exec);
+    g_graphs->pop_back();
+  }
+  g_graphs->push_front(GraphEntry{key, exec});
+  *out = exec;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pa_abi_version(void) { return PA_ABI_VERSION; }
+
+const char* pa_last_error(void) { return g_err.c_str(); }
+
+pa_status pa_validate_geometry(const pa_geometry* g, pa_dtype dtype) {
+  g_err.clear();
+  pa::Plan pl;
+  return plan_or_fail(g, dtype, &pl);
+}
+
+pa_status pa_forward(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = plan_or_fail(g, dtype, &pl);
+  if (st != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  PA_HIP(pa::launch_fill(dtype, y, pl.M, s), "zero y");
+  PA_HIP(pa::launch_forward_accumulate(pl, x, y, s), "forward kernel");
+  return PA_OK;
+}
+
+pa_status pa_adjoint(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = plan_or_fail(g, dtype, &pl);
+  if (st != PA_OK) return st;
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  PA_HIP(pa::launch_adjoint(pl, y, x, nullptr, s), "adjoint kernel");
+  return PA_OK;
+}
+
+size_t pa_cgls_workspace_bytes(const pa_geometry* g, pa_dtype dtype, int32_t iters) {
+  g_err.clear();
+  if (iters < 0) {
+    set_err(PA_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+    return 0;
+  }
+  pa::Plan pl;
+  if (plan_or_fail(g, dtype, &pl) != PA_OK) return 0;
+  return pa::cgls_layout(pl, iters).total;
+}
+
+pa_status pa_cgls_solve(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, int32_t iters, double lambda,
+                        uint32_t flags, void* workspace, size_t workspace_bytes, double* history, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = plan_or_fail(g, dtype, &pl);
+  if (st != PA_OK) return st;
+  if (iters < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+  if (iters > (1 << 20)) return set_err(PA_ERR_UNSUPPORTED, "iters above 2^20");
+  if (!std::isfinite(lambda) || lambda < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "lambda must be finite and >= 0");
+  if (flags & ~(PA_X0_ZERO | PA_USE_GRAPH)) return set_err(PA_ERR_INVALID_ARGUMENT, "unknown flag bits");
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if (history && !aligned(history, 8)) return set_err(PA_ERR_INVALID_ARGUMENT, "history is not 8-byte aligned");
+  const pa::CglsLayout L = pa::cgls_layout(pl, iters);
+  if (!workspace) return set_err(PA_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (workspace_bytes < L.total) return set_err(PA_ERR_WORKSPACE, "workspace smaller than pa_cgls_workspace_bytes()");
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  if (overlap(workspace, L.total, x, pl.P * pl.elem) || overlap(workspace, L.total, y, pl.M * pl.elem))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "workspace overlaps x or y");
+  if (history && (overlap(history, sizeof(double) * 3 * (size_t)(iters + 1), workspace, L.total) ||
+                  overlap(history, sizeof(double) * 3 * (size_t)(iters + 1), x, pl.P * pl.elem) ||
+                  overlap(history, sizeof(double) * 3 * (size_t)(iters + 1), y, pl.M * pl.elem)))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "history overlaps another buffer");
+
+  Solve S{&pl, L, y, x, iters, lambda, flags, static_cast<unsigned char*>(workspace), history};
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  bool use_graph = (flags & PA_USE_GRAPH) != 0;
+  if (use_graph && s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    PA_HIP(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) use_graph = false;  // already inside the caller's capture
+  }
+  if (!use_graph) {
+    PA_HIP(enqueue_cgls(S, s), "CGLS enqueue");
+    return PA_OK;
+  }
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.g = *g;
+  key.dt = dtype;
+  key.y = y;
+  key.x = x;
+  key.iters = iters;
+  key.lambda = lambda;
+  key.flags = flags;
+  key.ws = workspace;
+  key.hist = history;
+  PA_HIP(hipGetDevice(&key.device), "hipGetDevice");
+  hipGraphExec_t exec = nullptr;
+  PA_HIP(get_graph(key, S, &exec), "CGLS graph capture");
+  PA_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
+  return PA_OK;
+}
+
+pa_status pa_cgls_stop_iteration(const void* workspace, int32_t* stop_iter) {
+  g_err.clear();
+  if (!workspace || !stop_iter) return set_err(PA_ERR_INVALID_ARGUMENT, "NULL argument");
+  int v = -1;
+  PA_HIP(hipMemcpy(&v, workspace, sizeof(int), hipMemcpyDeviceToHost), "read CGLS status");
+  *stop_iter = v;
+  return v >= 0 ? PA_ERR_BREAKDOWN : PA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,193 @@
+// BLAS-1 and CGLS scalar kernels for gfx950.  Each reduction produces one
+// FP64 partial per work-group; consumers add the partials in a fixed order,
+// so every scalar of the solve is reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "pa_device.h"
+#include "pa_kernels.h"
+
+namespace pa {
+
+using dev::block_sum;
+using dev::sum_partials;
+
+// ---------------------------------------------------------------------------
+// BLAS-1 and CGLS scalar kernels.  Grids are fixed per vector length, so the
+// FP64 partial sums are always formed in the same order.
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fill_kernel(T* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) norm2_kernel(const T* __restrict__ v, int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const double a = (double)v[i];
+    acc += a * a;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// r = y - q (q may be NULL); partial sums of ||r||^2; resets the solve state.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) init_r_kernel(T* __restrict__ r, const T* __restrict__ y, const T* __restrict__ q,
+                                                        int64_t m, double* __restrict__ part_r, int* __restrict__ status,
+                                                        double* __restrict__ alpha0) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+    const double v = q ? (double)y[i] - (double)q[i] : (double)y[i];
+    const T t = (T)v;
+    r[i] = t;
+    acc += (double)t * (double)t;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    part_r[blockIdx.x] = acc;
+    if (blockIdx.x == 0) {
+      *status = -1;
+      *alpha0 = 0.0;
+    }
+  }
+}
+
+// delta = ||q||^2 + lambda ||p||^2, alpha = gamma_k / delta (0 once stopped),
+// r -= alpha q, partial sums of ||r||^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) upd_r_kernel(T* __restrict__ r, const T* __restrict__ q, int64_t m,
+                                                       const double* __restrict__ part_q, int gq,
+                                                       const double* __restrict__ part_p, int gp, double lambda,
+                                                       const double* __restrict__ gamma_k, double* __restrict__ alpha_k,
+                                                       int* __restrict__ status, int k, double* __restrict__ part_r) {
+  __shared__ double red[4];
+  const double qq = sum_partials(part_q, gq, red);
+  const double pp = sum_partials(part_p, gp, red);
+  const double delta = qq + lambda * pp;
+  const double g = *gamma_k;
+  const int st = *status;
+  const bool stop = st >= 0 || !(g > 0.0) || !(delta > 0.0) || !isfinite(g) || !isfinite(delta);
+  const double a = stop ? 0.0 : g / delta;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+    T t = r[i];
+    if (a != 0.0) {
+      t = (T)((double)t - a * (double)q[i]);
+      r[i] = t;
+    }
+    acc += (double)t * (double)t;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    part_r[blockIdx.x] = acc;
+    if (blockIdx.x == 0) {
+      *alpha_k = a;
+      if (stop && st < 0) *status = k;
+    }
+  }
+}
+
+// gamma_{k+1} = ||s||^2, beta = gamma_{k+1} / gamma_k (0 at the start or once
+// stopped), p = s + beta p, q = 0, history row k + 1, partial sums of ||p||^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) dir_kernel(T* __restrict__ p, const T* __restrict__ s, int64_t np,
+                                                     T* __restrict__ q, int64_t m,
+                                                     const double* __restrict__ part_s, int gs,
+                                                     const double* __restrict__ part_x, int gx,
+                                                     const double* __restrict__ part_r, int gr, double lambda,
+                                                     double* __restrict__ gamma, int k, const int* __restrict__ status,
+                                                     double* __restrict__ hist, double* __restrict__ part_p) {
+  __shared__ double red[4];
+  const double ss = sum_partials(part_s, gs, red);
+  const double xx = sum_partials(part_x, gx, red);
+  const double rr = sum_partials(part_r, gr, red);
+  double beta = 0.0;
+  if (k >= 0) {
+    const double gold = gamma[k];
+    beta = (*status >= 0 || !(gold > 0.0)) ? 0.0 : ss / gold;
+  }
+  double acc = 0.0;
+  const int64_t n = np > m ? np : m;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    if (i < np) {
+      const T t = (T)((double)s[i] + (beta != 0.0 ? beta * (double)p[i] : 0.0));
+      p[i] = t;
+      acc += (double)t * (double)t;
+    }
+    if (i < m) q[i] = (T)0;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    part_p[blockIdx.x] = acc;
+    if (blockIdx.x == 0) {
+      gamma[k + 1] = ss;
+      if (hist) {
+        hist[3 * (k + 1) + 0] = sqrt(rr);
+        hist[3 * (k + 1) + 1] = sqrt(ss);
+        hist[3 * (k + 1) + 2] = rr + lambda * xx;
+      }
+    }
+  }
+}
+
+hipError_t launch_fill(pa_dtype dt, void* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int g = blas_grid(n);
+  if (dt == PA_F32) fill_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(p), n);
+  else fill_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(pa_dtype dt, const void* v, int64_t n, double* part, hipStream_t st) {
+  const int g = blas_grid(n);
+  if (dt == PA_F32) norm2_kernel<float><<<g, kBlock, 0, st>>>(static_cast<const float*>(v), n, part);
+  else norm2_kernel<double><<<g, kBlock, 0, st>>>(static_cast<const double*>(v), n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_r(pa_dtype dt, void* r, const void* y, const void* q, int64_t m, double* part_r, int* status,
+                         double* alpha0, hipStream_t st) {
+  const int g = blas_grid(m);
+  if (dt == PA_F32)
+    init_r_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(r), static_cast<const float*>(y),
+                                               static_cast<const float*>(q), m, part_r, status, alpha0);
+  else
+    init_r_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(r), static_cast<const double*>(y),
+                                                static_cast<const double*>(q), m, part_r, status, alpha0);
+  return hipGetLastError();
+}
+
+hipError_t launch_upd_r(pa_dtype dt, void* r, const void* q, int64_t m, const double* part_q, int gq, const double* part_p,
+                        int gp, double lambda, const double* gamma_k, double* alpha_k, int* status, int k, double* part_r,
+                        hipStream_t st) {
+  const int g = blas_grid(m);
+  if (dt == PA_F32)
+    upd_r_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(r), static_cast<const float*>(q), m, part_q, gq, part_p,
+                                              gp, lambda, gamma_k, alpha_k, status, k, part_r);
+  else
+    upd_r_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(r), static_cast<const double*>(q), m, part_q, gq,
+                                               part_p, gp, lambda, gamma_k, alpha_k, status, k, part_r);
+  return hipGetLastError();
+}
+
+hipError_t launch_dir(pa_dtype dt, void* p, const void* s, int64_t np, void* q, int64_t m, const double* part_s, int gs,
+                      const double* part_x, int gx, const double* part_r, int gr, double lambda, double* gamma, int k,
+                      const int* status, double* hist, double* part_p, hipStream_t st) {
+  const int g = blas_grid(np);
+  if (dt == PA_F32)
+    dir_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(p), static_cast<const float*>(s), np,
+                                            static_cast<float*>(q), m, part_s, gs, part_x, gx, part_r, gr, lambda, gamma,
+                                            k, status, hist, part_p);
+  else
+    dir_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(p), static_cast<const double*>(s), np,
+                                             static_cast<double*>(q), m, part_s, gs, part_x, gx, part_r, gr, lambda,
+                                             gamma, k, status, hist, part_p);
+  return hipGetLastError();
+}
+
+}  // namespace pa

@@ -1,0 +1,190 @@
+// Host-side validation, unit conversion and tiling (no GPU access).
+#include "pa_plan.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <limits>
+
+namespace pa {
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+pa_status fail(std::string* msg, pa_status st, const char* text) {
+  if (msg) *msg = text;
+  return st;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+int blas_grid(int64_t n) {
+  int64_t g = (n + 1023) / 1024;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
+}
+
+pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg) {
+  if (!g) return fail(msg, PA_ERR_INVALID_ARGUMENT, "geometry pointer is NULL");
+  if (!plan) return fail(msg, PA_ERR_INVALID_ARGUMENT, "plan pointer is NULL");
+  if (dtype != PA_F32 && dtype != PA_F64) return fail(msg, PA_ERR_INVALID_ARGUMENT, "dtype must be PA_F32 or PA_F64");
+  if (g->ndim != 2 && g->ndim != 3) return fail(msg, PA_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  if (g->nx < 0 || g->ny < 0 || g->nz < 0) return fail(msg, PA_ERR_INVALID_ARGUMENT, "image sizes must be >= 0");
+  if (g->ndim == 2 && g->nz != 1) return fail(msg, PA_ERR_INVALID_ARGUMENT, "nz must be 1 for a 2D geometry");
+  if (g->n_sensors < 0 || g->n_samples < 0) return fail(msg, PA_ERR_INVALID_ARGUMENT, "n_sensors and n_samples must be >= 0");
+  if (!finite(g->h) || !(g->h > 0)) return fail(msg, PA_ERR_INVALID_ARGUMENT, "h must be finite and > 0");
+  if (!finite(g->dt) || !(g->dt > 0)) return fail(msg, PA_ERR_INVALID_ARGUMENT, "dt must be finite and > 0");
+  if (!finite(g->c) || !(g->c > 0)) return fail(msg, PA_ERR_INVALID_ARGUMENT, "c must be finite and > 0");
+  if (!finite(g->t0)) return fail(msg, PA_ERR_INVALID_ARGUMENT, "t0 must be finite");
+  if (!finite(g->r_min) || g->r_min < 0) return fail(msg, PA_ERR_INVALID_ARGUMENT, "r_min must be finite and >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!finite(g->center[a])) return fail(msg, PA_ERR_INVALID_ARGUMENT, "center must be finite");
+  if (g->n_sensors > 0 && !g->sensors) return fail(msg, PA_ERR_INVALID_ARGUMENT, "sensors is NULL but n_sensors > 0");
+  if (g->sensors && (reinterpret_cast<uintptr_t>(g->sensors) % 8) != 0)
+    return fail(msg, PA_ERR_INVALID_ARGUMENT, "sensors must be 8-byte aligned");
+
+  const int64_t P = (int64_t)g->nx * g->ny * g->nz;
+  const int64_t M = (int64_t)g->n_sensors * g->n_samples;
+  if (P > std::numeric_limits<int32_t>::max()) return fail(msg, PA_ERR_UNSUPPORTED, "more than 2^31-1 pixels");
+  if (M > std::numeric_limits<int32_t>::max()) return fail(msg, PA_ERR_UNSUPPORTED, "n_sensors * n_samples exceeds 2^31-1");
+  if (g->n_samples > (1 << 22)) return fail(msg, PA_ERR_UNSUPPORTED, "n_samples above 2^22");
+
+  const double inv_cdt = 1.0 / (g->c * g->dt);
+  const double hs = g->h * inv_cdt;
+  const double T0 = g->t0 / g->dt;
+  if (!finite(inv_cdt) || !finite(hs) || !(hs > 0)) return fail(msg, PA_ERR_INVALID_ARGUMENT, "h / (c dt) is not a finite positive number");
+  if (std::fabs(T0) > (double)(1 << 30)) return fail(msg, PA_ERR_UNSUPPORTED, "|t0 / dt| above 2^30");
+
+  Plan& pl = *plan;
+  pl = Plan{};
+  pl.ndim = g->ndim;
+  pl.dtype = dtype;
+  pl.elem = dtype == PA_F32 ? 4 : 8;
+  pl.P = P;
+  pl.M = M;
+  OpParams& op = pl.op;
+  op.nx = g->nx;
+  op.ny = g->ny;
+  op.nz = g->nz;
+  op.S = g->n_sensors;
+  op.K = g->n_samples;
+  op.hs = hs;
+  op.inv_cdt = inv_cdt;
+  op.rmin = (g->r_min > 0 ? g->r_min : 0.5 * g->h) * inv_cdt;
+  const double t0i = std::floor(T0);
+  op.t0i = (int32_t)t0i;
+  op.t0fd = T0 - t0i;
+  op.t0f = (float)op.t0fd;
+  if (op.t0f >= 1.0f) {  // rounding pushed the fraction to 1: carry it
+    op.t0i += 1;
+    op.t0fd = 0.0;
+    op.t0f = 0.0f;
+  }
+  op.sensors = g->sensors;
+  const int nd = g->ndim;
+  for (int a = 0; a < 3; ++a) {
+    int n = a == 0 ? g->nx : a == 1 ? g->ny : g->nz;
+    double c = (a < nd) ? g->center[a] : 0.0;
+    op.org[a] = (c - 0.5 * (n - 1) * g->h) * inv_cdt;
+  }
+  if (nd == 2) op.org[2] = 0.0;
+
+  const int TX = nd == 2 ? Tile<2>::X : Tile<3>::X;
+  const int TY = nd == 2 ? Tile<2>::Y : Tile<3>::Y;
+  const int TZ = nd == 2 ? Tile<2>::Z : Tile<3>::Z;
+  op.ntile[0] = ceil_div(g->nx, TX);
+  op.ntile[1] = ceil_div(g->ny, TY);
+  op.ntile[2] = ceil_div(g->nz, TZ);
+  op.n_tiles = op.ntile[0] * op.ntile[1] * op.ntile[2];
+
+  const size_t elem = pl.elem;
+  const size_t sc_bytes = dtype == PA_F32 ? 48 : 64;  // per-sensor constants in LDS (adjoint)
+
+  // Adjoint: window of one sensor over the base tile's pixel-centre box.  Any
+  // two pixels of the box differ in distance by at most its diagonal; the
+  // margins cover floor(), the second tap and FP32 rounding of the delay.
+  {
+    double ex = (TX - 1) * hs, ey = (TY - 1) * hs, ez = (TZ - 1) * hs;
+    double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
+    if (diag > 1e6) return fail(msg, PA_ERR_UNSUPPORTED, "pixel pitch spans too many samples");
+    op.wp = (int32_t)std::ceil(diag) + 5;
+    size_t per = sc_bytes + 4 + (size_t)op.wp * elem;
+    int64_t sc_max = (int64_t)(40 * 1024 / per);
+    if (sc_max < 1) sc_max = (int64_t)(kLdsBudget / per);
+    if (sc_max < 1) return fail(msg, PA_ERR_UNSUPPORTED, "trace window of one tile does not fit in LDS (h / (c dt) too large)");
+    sc_max = std::min<int64_t>(sc_max, kBlock);
+    int64_t S = std::max<int64_t>(g->n_sensors, 1);
+    int64_t nchunk = (S + sc_max - 1) / sc_max;
+    op.sc = (int32_t)((S + nchunk - 1) / nchunk);
+    op.wp_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)op.wp + 1);
+    pl.bp_lds = align_up((size_t)op.sc * sc_bytes, 16) + align_up((size_t)op.sc * 4, 16) +
+                (size_t)op.sc * op.wp * elem;
+  }
+
+  // Forward: histogram window of one sensor over a forward tile made of
+  // msub base tiles; shrink to a single base tile if it does not fit.
+  {
+    int cand[2][3] = {{2, 2, 1}, {1, 1, 1}};
+    if (nd == 3) { cand[0][0] = 2; cand[0][1] = 1; cand[0][2] = 2; }
+    bool ok = false;
+    for (auto& m : cand) {
+      double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
+      double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
+      int32_t wpa = ((int32_t)std::ceil(diag) + 5) | 1;  // odd stride spreads lanes over LDS banks
+      int nsub = m[0] * m[1] * m[2];
+      size_t lds = align_up((size_t)kSensorsPerFwdBlock * wpa * elem, 16) +
+                   (size_t)kBlock * (dtype == PA_F32 ? 16 : 32) +
+                   align_up((size_t)nsub * kBlock * elem, 16) + kSensorsPerFwdBlock * 4;
+      if (lds <= kLdsBudget) {
+        for (int a = 0; a < 3; ++a) op.msub[a] = m[a];
+        op.nsub = nsub;
+        op.wpa = wpa;
+        pl.fp_lds = lds;
+        ok = true;
+        break;
+      }
+    }
+    if (!ok) return fail(msg, PA_ERR_UNSUPPORTED, "histogram window of one tile does not fit in LDS (h / (c dt) too large)");
+    for (int a = 0; a < 3; ++a) op.natile[a] = ceil_div(op.ntile[a], op.msub[a]);
+    op.n_atiles = op.natile[0] * op.natile[1] * op.natile[2];
+    op.n_chunks = ceil_div(g->n_sensors, kSensorsPerFwdBlock);
+  }
+
+  op.out_scale = (float)(2.0 * inv_cdt);   // float path accumulates w / 2
+  op.out_scale_d = inv_cdt;                // double path accumulates w
+  // The adjoint runs whenever there are pixels (with no sensors or samples it
+  // writes zeros, and its CGLS epilogue still has work); the forward
+  // operator only when there is something to scatter.
+  const bool empty = P == 0 || g->n_sensors == 0 || g->n_samples == 0;
+  pl.bp_grid = P == 0 ? 0 : op.n_tiles;
+  pl.fp_grid = empty ? 0 : op.n_atiles * op.n_chunks;
+  return PA_OK;
+}
+
+CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
+  CglsLayout L{};
+  const size_t A = 256;
+  L.g_m = blas_grid(plan.M);
+  L.g_p = blas_grid(plan.P);
+  L.g_bp = std::max(plan.op.n_tiles, 1);
+  size_t off = 0;
+  L.status = off; off = align_up(off + 64, A);
+  L.gamma = off; off = align_up(off + sizeof(double) * (size_t)(iters + 2), A);
+  L.alpha = off; off = align_up(off + sizeof(double) * (size_t)(iters + 2), A);
+  L.part_q = off; off = align_up(off + sizeof(double) * L.g_m, A);
+  L.part_r = off; off = align_up(off + sizeof(double) * L.g_m, A);
+  L.part_s = off; off = align_up(off + sizeof(double) * L.g_bp, A);
+  L.part_x = off; off = align_up(off + sizeof(double) * L.g_bp, A);
+  L.part_p = off; off = align_up(off + sizeof(double) * L.g_p, A);
+  L.vec_r = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
+  L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
+  L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.vec_p = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.total = off;
+  return L;
+}
+
+}  // namespace pa

@@ -1,0 +1,79 @@
+// Host-side planning shared by every entry point: validation of a geometry,
+// conversion to sample units, tiling and LDS budgets.  Plain C++ with no HIP
+// calls, so it runs (and is tested) without a GPU.
+#pragma once
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "pa.h"
+
+namespace pa {
+
+// Base tiles: one work-group of 256 lanes, one pixel per lane.
+//   2D: 16 x 16 x 1      3D: 8 x 8 x 4
+template <int ND> struct Tile;
+template <> struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4; };
+
+constexpr int kBlock = 256;          // lanes per work-group, every kernel
+constexpr int kSensorsPerFwdBlock = 64;  // forward operator: one sensor per lane of a wave
+constexpr size_t kLdsBudget = 64 * 1024 - 256;  // dynamic LDS per work-group (static LDS rides on top)
+
+// Everything a kernel needs about the operator, by value.  Lengths are in
+// "sample units": metres multiplied by 1 / (c dt), so a distance equals its
+// delay in samples.
+struct OpParams {
+  int32_t nx, ny, nz;       // image size
+  int32_t S, K;             // sensors, samples
+  double org[3];            // position of pixel (0,0,0), sample units
+  double hs;                // pixel pitch, sample units
+  double rmin;              // distance clamp, sample units
+  double inv_cdt;           // metres -> sample units
+  int32_t t0i;              // floor(t0 / dt)
+  float t0f;                // t0 / dt - t0i, in [0, 1)
+  double t0fd;
+  const double* sensors;    // device, [S][ndim], metres
+  int32_t ntile[3];         // base tiles per axis
+  int32_t n_tiles;          // product
+  int32_t wp;               // adjoint: LDS window stride (samples) of one sensor
+  int32_t sc;               // adjoint: sensors staged per chunk
+  uint32_t wp_magic;        // ceil(2^32 / wp) for index division
+  int32_t msub[3];          // forward: base tiles per forward tile, per axis
+  int32_t nsub;             // product
+  int32_t natile[3];        // forward tiles per axis
+  int32_t n_atiles;
+  int32_t n_chunks;         // forward: sensor chunks of 64
+  int32_t wpa;              // forward: LDS histogram stride of one sensor
+  float out_scale;          // converts accumulated kernel units to 1/metres (float path)
+  double out_scale_d;       // same, double path
+};
+
+struct Plan {
+  OpParams op;
+  int ndim;
+  pa_dtype dtype;
+  size_t elem;              // sizeof(T)
+  int64_t P, M;             // pixels, samples (S*K)
+  size_t bp_lds, fp_lds;    // dynamic LDS bytes
+  int bp_grid, fp_grid;
+};
+
+// Fills *plan from g.  Returns PA_OK or an error with *msg set.  Never touches
+// the GPU or dereferences g->sensors.
+pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg);
+
+// Sizes of the BLAS-1 grids (fixed per vector length so every reduction runs
+// in the same order every time).
+int blas_grid(int64_t n);
+
+// CGLS workspace layout.
+struct CglsLayout {
+  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, total;
+  int g_m, g_p, g_bp;       // partial counts: over S*K, over pixels, adjoint tiles
+};
+CglsLayout cgls_layout(const Plan& plan, int32_t iters);
+
+}  // namespace pa

@@ -1,0 +1,232 @@
+"""Python entry points over the C ABI: forward (A), adjoint (A^T) and CGLS.
+
+Argument marshalling only: tensors must already live on the HIP device; the
+kernels run on the current torch stream.  Image tensors have shape
+(ny, nx) or (nz, ny, nx) (or flat), measurement tensors (S, K); float32 selects
+PA_F32, float64 selects PA_F64.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+class DeviceGeometry:
+    """Grid, sensor array and timing, with the sensor table on the device.
+
+    Accepts any object exposing ndim, nx, ny, nz, h, center, sensors
+    ([S][ndim] metres), n_samples, dt, t0, c, r_min.
+    """
+
+    def __init__(self, g, device=None):
+        device = torch.device("cuda") if device is None else torch.device(device)
+        self.ndim = int(g.ndim)
+        self.nx, self.ny, self.nz = int(g.nx), int(g.ny), int(g.nz)
+        self.h = float(g.h)
+        ctr = list(g.center) + [0.0] * (3 - len(g.center))
+        self.center = tuple(float(v) for v in ctr[:3])
+        sens = g.sensors
+        if not isinstance(sens, torch.Tensor):
+            sens = torch.from_numpy(np.ascontiguousarray(np.asarray(sens, dtype=np.float64)))
+        self.sensors = sens.to(device=device, dtype=torch.float64).contiguous().reshape(-1, self.ndim)
+        self.n_samples = int(g.n_samples)
+        self.dt, self.t0, self.c, self.r_min = float(g.dt), float(g.t0), float(g.c), float(g.r_min)
+        self.device = device
+
+    @property
+    def n_sensors(self) -> int:
+        return int(self.sensors.shape[0])
+
+    @property
+    def n_pixels(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def image_shape(self) -> tuple:
+        return (self.ny, self.nx) if self.ndim == 2 else (self.nz, self.ny, self.nx)
+
+    @property
+    def data_shape(self) -> tuple:
+        return (self.n_sensors, self.n_samples)
+
+    def c_struct(self) -> _lib.PaGeometry:
+        s = _lib.PaGeometry()
+        s.ndim, s.nx, s.ny, s.nz = self.ndim, self.nx, self.ny, self.nz
+        s.h = self.h
+        s.center = (ctypes.c_double * 3)(*self.center)
+        s.n_sensors = self.n_sensors
+        s.sensors = self.sensors.data_ptr() if self.n_sensors else None
+        s.n_samples = self.n_samples
+        s.dt, s.t0, s.c, s.r_min = self.dt, self.t0, self.c, self.r_min
+        return s
+
+
+def as_device_geometry(g, device=None) -> DeviceGeometry:
+    return g if isinstance(g, DeviceGeometry) else DeviceGeometry(g, device)
+
+
+def _code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return _lib.PA_F32
+    if t.dtype == torch.float64:
+        return _lib.PA_F64
+    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+
+
+def _stream(dev) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _check_tensor(t: torch.Tensor, numel: int, name: str):
+    if not (t.is_cuda or t.numel() == 0):
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def _frames(t: torch.Tensor, per: int):
+    """Split a contiguous tensor into frames of `per` elements (one frame if it holds exactly one)."""
+    if per == 0:
+        return [t.reshape(-1)], ()
+    if t.numel() % per != 0:
+        raise ValueError(f"tensor with {t.numel()} elements is not a whole number of frames of {per}")
+    nb = t.numel() // per
+    return list(t.reshape(nb, per)), nb
+
+
+def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Tensor:
+    """y := A x.  Leading batch dimensions of x are applied frame by frame."""
+    g = as_device_geometry(geom, x.device)
+    P, M = g.n_pixels, g.n_sensors * g.n_samples
+    x = x.contiguous()
+    batch = tuple(x.shape[: x.dim() - len(g.image_shape)]) if x.dim() > len(g.image_shape) else ()
+    if out is None:
+        out = torch.empty(batch + g.data_shape, dtype=x.dtype, device=x.device)
+    _check_tensor(out, out.numel(), "y")
+    xs, nb = _frames(x, P)
+    ys, nb2 = _frames(out, M) if M else ([out.reshape(-1)] * len(xs), nb)
+    if M and len(xs) != len(ys):
+        raise ValueError("x and y hold different numbers of frames")
+    lib = _lib.load()
+    cg = g.c_struct()
+    for xb, yb in zip(xs, ys):
+        _lib.check(lib.pa_forward(ctypes.byref(cg), _code(x), xb.data_ptr() or None, yb.data_ptr() or None,
+                                  _stream(x.device)))
+    return out
+
+
+def adjoint(y: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Tensor:
+    """x := A^T y.  Leading batch dimensions of y are applied frame by frame."""
+    g = as_device_geometry(geom, y.device)
+    P, M = g.n_pixels, g.n_sensors * g.n_samples
+    y = y.contiguous()
+    batch = tuple(y.shape[:-2]) if y.dim() > 2 else ()
+    if out is None:
+        out = torch.empty(batch + g.image_shape, dtype=y.dtype, device=y.device)
+    _check_tensor(out, out.numel(), "x")
+    ys, nb = _frames(y, M)
+    xs, nb2 = _frames(out, P) if P else ([out.reshape(-1)] * len(ys), nb)
+    if P and len(xs) != len(ys):
+        raise ValueError("x and y hold different numbers of frames")
+    lib = _lib.load()
+    cg = g.c_struct()
+    for yb, xb in zip(ys, xs):
+        _lib.check(lib.pa_adjoint(ctypes.byref(cg), _code(y), yb.data_ptr() or None, xb.data_ptr() or None,
+                                  _stream(y.device)))
+    return out
+
+
+class Operator:
+    """A and A^T on one geometry with the argument struct built once (low call overhead).
+
+    forward_(x, y) and adjoint_(y, x) write into preallocated contiguous device
+    tensors of the operator's dtype and skip the shape bookkeeping of
+    forward()/adjoint().
+    """
+
+    def __init__(self, geom, dtype: torch.dtype = torch.float32, device=None):
+        self.geom = as_device_geometry(geom, device)
+        self.dtype = dtype
+        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._cg = self.geom.c_struct()
+        self._ref = ctypes.byref(self._cg)
+        self._lib = _lib.load()
+        _lib.check(self._lib.pa_validate_geometry(self._ref, self._code))
+
+    def forward_(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        _lib.check(self._lib.pa_forward(self._ref, self._code, x.data_ptr() or None, y.data_ptr() or None,
+                                        torch.cuda.current_stream(x.device).cuda_stream))
+        return y
+
+    def adjoint_(self, y: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+        _lib.check(self._lib.pa_adjoint(self._ref, self._code, y.data_ptr() or None, x.data_ptr() or None,
+                                        torch.cuda.current_stream(y.device).cuda_stream))
+        return x
+
+
+def cgls_workspace_bytes(geom, dtype: torch.dtype, iters: int) -> int:
+    g = as_device_geometry(geom)
+    lib = _lib.load()
+    code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+    n = lib.pa_cgls_workspace_bytes(ctypes.byref(g.c_struct()), code, int(iters))
+    if n == 0:
+        raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
+    return int(n)
+
+
+class CglsSolver:
+    """Owns the device workspace and history of repeated solves on one geometry."""
+
+    def __init__(self, geom, dtype: torch.dtype, iters: int, lam: float, graph: bool = True, device=None):
+        self.geom = as_device_geometry(geom, device)
+        self.dtype = dtype
+        self.iters = int(iters)
+        self.lam = float(lam)
+        self.graph = graph
+        dev = self.geom.device
+        nbytes = cgls_workspace_bytes(self.geom, dtype, self.iters)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.history = torch.zeros((self.iters + 1, 3), dtype=torch.float64, device=dev)
+        self._cg = self.geom.c_struct()
+
+    def solve(self, y: torch.Tensor, x: torch.Tensor | None = None, x0_zero: bool = True) -> torch.Tensor:
+        g = self.geom
+        if x is None:
+            x = torch.empty(g.image_shape, dtype=self.dtype, device=y.device)
+            x0_zero = True
+        _check_tensor(y, g.n_sensors * g.n_samples, "y")
+        _check_tensor(x, g.n_pixels, "x")
+        if y.dtype != self.dtype or x.dtype != self.dtype:
+            raise TypeError("y and x must match the solver dtype")
+        flags = (_lib.PA_X0_ZERO if x0_zero else 0) | (_lib.PA_USE_GRAPH if self.graph else 0)
+        lib = _lib.load()
+        _lib.check(lib.pa_cgls_solve(ctypes.byref(self._cg), _code(y), y.data_ptr() or None, x.data_ptr() or None,
+                                     self.iters, self.lam, flags, self.workspace.data_ptr(),
+                                     self.workspace.numel(), self.history.data_ptr(), _stream(y.device)))
+        return x
+
+    def stop_iteration(self) -> int:
+        """-1 if the last solve ran every iteration, else the iteration it stopped at (synchronises)."""
+        torch.cuda.synchronize(self.geom.device)
+        out = ctypes.c_int32(-1)
+        _lib.check(_lib.load().pa_cgls_stop_iteration(self.workspace.data_ptr(), ctypes.byref(out)),
+                   allow=(_lib.PA_OK, _lib.PA_ERR_BREAKDOWN))
+        return int(out.value)
+
+
+def cgls(y: torch.Tensor, geom, iters: int, lam: float, x0: torch.Tensor | None = None, graph: bool = True):
+    """CGLS on ||A x - y||^2 + lam ||x||^2.  Returns (x, history[iters+1][3], stop_iteration)."""
+    solver = CglsSolver(geom, y.dtype, iters, lam, graph=graph, device=y.device)
+    if x0 is None:
+        x = solver.solve(y.contiguous())
+    else:
+        x = x0.detach().clone().contiguous()
+        solver.solve(y.contiguous(), x, x0_zero=False)
+    stop = solver.stop_iteration()
+    return x, solver.history.clone(), stop

@@ -1,0 +1,119 @@
+"""The C ABI library loads, exports every function include/pa.h declares, and
+rejects bad arguments on the host before touching a GPU (CPU-only test)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pa.h")
+LIB = os.path.join(ROOT, "paper_2404_10928_amd", "libpa_mi355x.so")
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double), ("center", ctypes.c_double * 3), ("n_sensors", ctypes.c_int32),
+                ("sensors", ctypes.c_void_p), ("n_samples", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("t0", ctypes.c_double), ("c", ctypes.c_double), ("r_min", ctypes.c_double)]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2404_10928_amd.build import build
+        build()
+    l = ctypes.CDLL(LIB)
+    gp = ctypes.POINTER(Geom)
+    l.pa_validate_geometry.argtypes = [gp, ctypes.c_int]
+    l.pa_forward.argtypes = [gp, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    l.pa_adjoint.argtypes = [gp, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    l.pa_cgls_workspace_bytes.argtypes = [gp, ctypes.c_int, ctypes.c_int32]
+    l.pa_cgls_workspace_bytes.restype = ctypes.c_size_t
+    l.pa_cgls_solve.argtypes = [gp, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+    l.pa_last_error.restype = ctypes.c_char_p
+    l.pa_cgls_stop_iteration.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+    return l
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(pa_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"pa_forward", "pa_adjoint", "pa_cgls_solve", "pa_cgls_workspace_bytes"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.pa_abi_version() == 1
+
+
+def good():
+    g = Geom()
+    g.ndim, g.nx, g.ny, g.nz = 2, 64, 48, 1
+    g.h = 1e-4
+    g.center = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    g.n_sensors = 32
+    g.sensors = 4096          # never dereferenced on the host
+    g.n_samples = 300
+    g.dt, g.t0, g.c, g.r_min = 25e-9, 0.0, 1500.0, 0.0
+    return g
+
+
+BAD = [
+    ("ndim", 4, 1), ("nz", 3, 1), ("nx", -1, 1), ("n_sensors", -2, 1), ("n_samples", -1, 1),
+    ("h", 0.0, 1), ("h", float("nan"), 1), ("dt", -1e-9, 1), ("c", float("inf"), 1), ("t0", float("nan"), 1),
+    ("r_min", -1e-6, 1), ("sensors", 0, 1), ("sensors", 4097, 1), ("n_samples", (1 << 22) + 1, 2),
+    ("dt", 1e-15, 2),  # h / (c dt) so large a single tile's window cannot fit in LDS
+]
+
+
+@pytest.mark.parametrize("field,value,code", BAD, ids=[f"{f}={v}" for f, v, _ in BAD])
+def test_invalid_geometry_rejected_on_host(lib, field, value, code):
+    g = good()
+    setattr(g, field, value)
+    assert lib.pa_validate_geometry(ctypes.byref(g), 0) == code
+    assert lib.pa_last_error()
+    # the operator entry points fail the same way, before any HIP call
+    assert lib.pa_forward(ctypes.byref(g), 0, 256, 1 << 20, None) == code
+    assert lib.pa_adjoint(ctypes.byref(g), 0, 1 << 20, 256, None) == code
+    assert lib.pa_cgls_workspace_bytes(ctypes.byref(g), 0, 10) == 0
+
+
+def test_valid_geometry_and_workspace(lib):
+    g = good()
+    assert lib.pa_validate_geometry(ctypes.byref(g), 0) == 0
+    assert lib.pa_last_error() == b""
+    n32 = lib.pa_cgls_workspace_bytes(ctypes.byref(g), 0, 20)
+    n64 = lib.pa_cgls_workspace_bytes(ctypes.byref(g), 1, 20)
+    P, M = 64 * 48, 32 * 300
+    assert n32 >= 4 * (2 * P + 2 * M) and n64 >= 8 * (2 * P + 2 * M) and n64 > n32
+    assert lib.pa_validate_geometry(None, 0) == 1
+    assert lib.pa_validate_geometry(ctypes.byref(g), 7) == 1
+
+
+def test_pointer_and_argument_checks_on_host(lib):
+    g = good()
+    # NULL / misaligned / overlapping buffers
+    assert lib.pa_forward(ctypes.byref(g), 0, None, 1 << 20, None) == 1
+    assert lib.pa_forward(ctypes.byref(g), 0, 256 + 2, 1 << 20, None) == 1
+    assert lib.pa_forward(ctypes.byref(g), 0, 1 << 20, (1 << 20) + 64, None) == 1
+    assert lib.pa_adjoint(ctypes.byref(g), 1, 1 << 20, 256 + 4, None) == 1
+    ws = lib.pa_cgls_workspace_bytes(ctypes.byref(g), 0, 5)
+    base = 1 << 30
+    args = lambda **kw: dict(dict(it=5, lam=1e-3, flags=1, ws=base, wsb=ws), **kw)
+    def solve(a):
+        return lib.pa_cgls_solve(ctypes.byref(g), 0, 1 << 20, 1 << 24, a["it"], a["lam"], a["flags"], a["ws"],
+                                 a["wsb"], None, None)
+    assert solve(args(it=-1)) == 1
+    assert solve(args(lam=-1.0)) == 1
+    assert solve(args(lam=float("nan"))) == 1
+    assert solve(args(flags=8)) == 1
+    assert solve(args(ws=None)) == 3
+    assert solve(args(ws=base + 16)) == 3
+    assert solve(args(wsb=ws - 1)) == 3
+    stop = ctypes.c_int32()
+    assert lib.pa_cgls_stop_iteration(None, ctypes.byref(stop)) == 1

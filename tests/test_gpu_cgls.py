@@ -1,0 +1,123 @@
+"""GPU CGLS against the FP64 oracle solve.
+
+Gates (see the precision reading in the design notes): a PA_F64 solve must
+match the oracle iterate to 1e-4 relative L2 (it lands far closer); a PA_F32
+solve must match the objective F(x_k) and the residual norm ||r_k|| to 1e-4 at
+every iteration, while its iterate error is reported, since CG amplifies the
+FP32 rounding of each apply.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import rel_l2, ring_geom, rounded
+from synth import add_noise, make_config
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pa():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    import paper_2404_10928_amd.ops as ops
+    return ops
+
+
+def problem(w):
+    g = w.geom
+    y = add_noise(oracle.forward(g, w.x_true), w.noise_rel, w.noise_seeds[0])
+    return g, y
+
+
+def gpu_cgls(pa, g, y, iters, lam, dtype, graph=True, x0=None):
+    yt = torch.from_numpy(np.ascontiguousarray(y.astype(dtype))).to("cuda")
+    x0t = None if x0 is None else torch.from_numpy(np.ascontiguousarray(x0.astype(dtype))).to("cuda")
+    x, hist, stop = pa.cgls(yt, g, iters, lam, x0=x0t, graph=graph)
+    return x.cpu().numpy().astype(np.float64), hist.cpu().numpy(), stop
+
+
+def test_c1_f64_iterate(pa):
+    w = make_config("C1")
+    g, y = problem(w)
+    x_ref, h_ref, stop_ref = oracle.cgls(g, y, w.iters, w.lam)
+    x, h, stop = gpu_cgls(pa, g, y, w.iters, w.lam, np.float64)
+    e = rel_l2(x, x_ref)
+    print(f"C1 F64: iterate {e:.3e}, F_N {h[-1, 2]:.6e} vs {h_ref[-1, 2]:.6e}")
+    assert stop == -1 and stop_ref == w.iters
+    assert e <= 1e-4
+    np.testing.assert_allclose(h, h_ref, rtol=1e-8)
+
+
+def test_c1_f32_history(pa):
+    w = make_config("C1")
+    g, y = problem(w)
+    y32, y64 = rounded(y, np.float32)
+    x_ref, h_ref, _ = oracle.cgls(g, y64, w.iters, w.lam)
+    x, h, stop = gpu_cgls(pa, g, y32, w.iters, w.lam, np.float32)
+    eF = np.max(np.abs(h[:, 2] / h_ref[:, 2] - 1))
+    eR = np.max(np.abs(h[:, 0] / h_ref[:, 0] - 1))
+    print(f"C1 F32: max F err {eF:.2e}, max ||r|| err {eR:.2e}, iterate {rel_l2(x, x_ref):.2e}")
+    assert eF <= 1e-4 and eR <= 1e-4
+
+
+def test_c2_f32_history(pa):
+    w = make_config("C2")
+    g, y = problem(w)
+    y32, y64 = rounded(y, np.float32)
+    x_ref, h_ref, _ = oracle.cgls(g, y64, w.iters, w.lam)
+    x, h, stop = gpu_cgls(pa, g, y32, w.iters, w.lam, np.float32)
+    eF = np.max(np.abs(h[:, 2] / h_ref[:, 2] - 1))
+    eR = np.max(np.abs(h[:, 0] / h_ref[:, 0] - 1))
+    print(f"C2 F32: max F err {eF:.2e}, max ||r|| err {eR:.2e}, iterate rel-L2 {rel_l2(x, x_ref):.2e}")
+    assert stop == -1
+    assert eF <= 1e-4 and eR <= 1e-4
+
+
+def test_graph_matches_eager(pa):
+    g = ring_geom(n=(64, 48), S=96, K=320)
+    rng = np.random.default_rng(21)
+    y = oracle.forward(g, rng.uniform(size=g.image_shape)) + 0.01 * rng.normal(size=g.data_shape)
+    xa, ha, _ = gpu_cgls(pa, g, y, 12, 1e-3, np.float64, graph=True)
+    xb, hb, _ = gpu_cgls(pa, g, y, 12, 1e-3, np.float64, graph=False)
+    # replay the cached graph a second time with eager work in between
+    xc, hc, _ = gpu_cgls(pa, g, y, 12, 1e-3, np.float64, graph=True)
+    x_ref, h_ref, _ = oracle.cgls(g, y, 12, 1e-3)
+    for x, h in ((xa, ha), (xb, hb), (xc, hc)):
+        assert rel_l2(x, x_ref) <= 1e-8
+        np.testing.assert_allclose(h, h_ref, rtol=1e-9)
+
+
+def test_warm_start_and_regularisation(pa):
+    g = ring_geom(n=(40, 40), S=64, K=300)
+    rng = np.random.default_rng(22)
+    y = oracle.forward(g, rng.uniform(size=g.image_shape))
+    x0 = rng.uniform(size=g.image_shape)
+    for lam in (0.0, 50.0):
+        x_ref, h_ref, _ = oracle.cgls(g, y, 8, lam, x0=x0)
+        x, h, _ = gpu_cgls(pa, g, y, 8, lam, np.float64, x0=x0)
+        assert rel_l2(x, x_ref) <= 1e-8
+        np.testing.assert_allclose(h, h_ref, rtol=1e-8)
+
+
+def test_breakdown_zero_data(pa):
+    g = ring_geom(n=(16, 16), S=8, K=100)
+    for dt in (np.float32, np.float64):
+        x, h, stop = gpu_cgls(pa, g, np.zeros(g.data_shape), 5, 1e-3, dt)
+        assert stop == 0
+        assert np.all(x == 0) and np.all(h == 0)
+
+
+def test_zero_iterations_and_no_sensors(pa):
+    g = ring_geom(n=(16, 16), S=8, K=100)
+    rng = np.random.default_rng(23)
+    y = rng.normal(size=g.data_shape)
+    x, h, stop = gpu_cgls(pa, g, y, 0, 1e-3, np.float64)
+    assert np.all(x == 0)
+    np.testing.assert_allclose(h[0, 0], np.linalg.norm(y), rtol=1e-12)
+    # no sensors: min lambda ||x||^2 from a warm start reaches 0 in one step
+    g0 = g.replace(sensors=np.zeros((0, 2)))
+    x0 = rng.uniform(size=g.image_shape)
+    x, h, stop = gpu_cgls(pa, g0, np.zeros((0, 100)), 3, 0.5, np.float64, x0=x0)
+    assert np.max(np.abs(x)) <= 1e-12
