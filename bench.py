@@ -72,7 +72,7 @@ def main():
     pairs = P * S
 
     # synthetic data: y = A x_true + 1% noise, generated on the GPU path itself
-    x_true = torch.from_numpy(w.x_true.astype(np.float32)).to(dev)
+    x_true = torch.from_numpy(w.x.astype(np.float32)).to(dev)
     y_clean = pa.forward(x_true, geom)
     torch.cuda.synchronize()
     y_np = add_noise(y_clean.double().cpu().numpy(), w.noise_rel, w.noise_seeds[0])

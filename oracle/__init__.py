@@ -54,6 +54,8 @@ def _configure(lib):
                                 ctypes.c_int]
         lib.or_landweber.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      dp, ctypes.c_int]
+        lib.or_tv2d.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, dp]
+        lib.or_tv2d.restype = ctypes.c_double
     return lib
 
 
@@ -150,3 +152,23 @@ def landweber(g, y, iters, lam, omega, threads=None):
                         _dp(hist), _threads(threads)) != 0:
         raise ValueError("oracle: bad arguments")
     return x, hist
+
+
+def tv2d(x, eps=1e-8):
+    """(TV_eps(x), dTV/dx) of one 2D image in FP64."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.ndim == 2
+    g = np.empty_like(x)
+    v = lib.or_tv2d(_dp(x), x.shape[1], x.shape[0], float(eps), _dp(g))
+    return v, g
+
+
+def loss_gradient(g, x, y, tv_weight, eps=1e-8, threads=None):
+    """FP64 value and gradient of ||A x - y||^2 + tv_weight * TV_eps(x) for one 2D frame:
+    gradient = 2 A^T (A x - y) + tv_weight * dTV/dx."""
+    r = forward(g, x, threads) - np.asarray(y, dtype=np.float64).reshape(g.data_shape)
+    tvv, tvg = tv2d(np.asarray(x, dtype=np.float64).reshape(g.image_shape), eps)
+    val = float(np.sum(r * r)) + tv_weight * tvv
+    grad = 2.0 * adjoint(g, r, threads) + tv_weight * tvg
+    return val, grad

@@ -220,3 +220,33 @@ int or_landweber(const or_geom* g, const double* y, double* x, int iters, double
   free(r); free(s);
   return 0;
 }
+
+/* TV_eps(x) = sum_p m_p, m_p = sqrt(dx_p^2 + dy_p^2 + eps^2),
+ * dx_p = x[iy][ix+1] - x[iy][ix] (0 in the last column), dy_p likewise.
+ * dTV/dx[q] collects, from every m_p whose differences contain x[q],
+ * (d m_p / d dx_p) * (d dx_p / d x[q]) + (d m_p / d dy_p) * (d dy_p / d x[q]). */
+double or_tv2d(const double* x, int32_t nx, int32_t ny, double eps, double* grad) {
+  double tv = 0.0;
+  if (grad)
+    for (int64_t i = 0; i < (int64_t)nx * ny; ++i) grad[i] = 0.0;
+  for (int32_t iy = 0; iy < ny; ++iy) {
+    for (int32_t ix = 0; ix < nx; ++ix) {
+      const int64_t p = (int64_t)iy * nx + ix;
+      const double dx = ix + 1 < nx ? x[p + 1] - x[p] : 0.0;
+      const double dy = iy + 1 < ny ? x[p + nx] - x[p] : 0.0;
+      const double m = sqrt(dx * dx + dy * dy + eps * eps);
+      tv += m;
+      if (grad) {
+        if (ix + 1 < nx) {
+          grad[p + 1] += dx / m;
+          grad[p] -= dx / m;
+        }
+        if (iy + 1 < ny) {
+          grad[p + nx] += dy / m;
+          grad[p] -= dy / m;
+        }
+      }
+    }
+  }
+  return tv;
+}

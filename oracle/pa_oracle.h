@@ -54,6 +54,12 @@ int or_cgls(const or_geom* g, const double* y, double* x, int iters, double lamb
 int or_landweber(const or_geom* g, const double* y, double* x, int iters, double lambda,
                  double omega, double* hist, int threads);
 
+/* Isotropic smoothed total variation of one 2D image [ny][nx] (the TV term of
+ * the paper's objective, Eq. 8): TV = sum_p sqrt(dx_p^2 + dy_p^2 + eps^2) with
+ * forward differences, zero past the last column / row.  Returns TV and, if
+ * grad is not NULL, writes dTV/dx. */
+double or_tv2d(const double* x, int32_t nx, int32_t ny, double eps, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

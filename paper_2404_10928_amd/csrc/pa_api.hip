@@ -87,6 +87,7 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
   void* q = ws + L.vec_q;
   void* s = ws + L.vec_s;
   void* p = ws + L.vec_p;
+  void* fwd = ws + L.fwd;
   hipError_t e;
   const int gbp = std::max(pl.bp_grid, 1);
 
@@ -95,8 +96,7 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
     if ((e = pa::launch_fill(dt, S.x, pl.P, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, nullptr, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
   } else {
-    if ((e = pa::launch_fill(dt, q, pl.M, st)) != hipSuccess) return e;
-    if ((e = pa::launch_forward_accumulate(pl, S.x, q, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
   }
   pa::CgArgs cg{S.x, p, alpha, S.lambda, part_s, part_x};
@@ -111,17 +111,17 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
     return pa::launch_adjoint(pl, r, s, &c2, st);
   };
   if ((e = adjoint_cg(alpha)) != hipSuccess) return e;
-  if ((e = pa::launch_dir(dt, p, s, pl.P, q, pl.M, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma, -1,
+  if ((e = pa::launch_dir(dt, p, s, pl.P, nullptr, 0, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma, -1,
                           status, S.hist, part_p, st)) != hipSuccess)
     return e;
   for (int k = 0; k < S.iters; ++k) {
-    if ((e = pa::launch_forward_accumulate(pl, p, q, st)) != hipSuccess) return e;
-    if ((e = pa::launch_norm2(dt, q, pl.M, part_q, st)) != hipSuccess) return e;
-    if ((e = pa::launch_upd_r(dt, r, q, pl.M, part_q, L.g_m, part_p, L.g_p, S.lambda, gamma + k, alpha + k + 1, status,
+    // q = A p with the FP64 partials of ||q||^2 (the forward gather overwrites q)
+    if ((e = pa::launch_forward(pl, p, q, fwd, part_q, st)) != hipSuccess) return e;
+    if ((e = pa::launch_upd_r(dt, r, q, pl.M, part_q, L.g_q, part_p, L.g_p, S.lambda, gamma + k, alpha + k + 1, status,
                               k, part_r, st)) != hipSuccess)
       return e;
     if ((e = adjoint_cg(alpha + k + 1)) != hipSuccess) return e;
-    if ((e = pa::launch_dir(dt, p, s, pl.P, q, pl.M, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma, k,
+    if ((e = pa::launch_dir(dt, p, s, pl.P, nullptr, 0, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma, k,
                             status, S.hist, part_p, st)) != hipSuccess)
       return e;
   }
@@ -190,6 +190,49 @@ hipError_t get_graph(const GraphKey& key, const Solve& S, hipGraphExec_t* out) {
   return hipSuccess;
 }
 
+// ------------------------------------------------- forward-operator scratch
+//
+// pa_forward keeps one scratch buffer per (device, stream) for the partial
+// histogram rows of the forward operator, grown on demand and kept until the
+// process ends.  Calls on one stream are ordered, so they can share it.
+
+struct ScratchEntry {
+  int device;
+  hipStream_t stream;
+  void* ptr;
+  size_t bytes;
+};
+std::mutex g_scr_mu;
+std::list<ScratchEntry>* g_scr = nullptr;
+
+hipError_t get_scratch(size_t bytes, hipStream_t st, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  if (!g_scr) g_scr = new std::list<ScratchEntry>();
+  for (auto& en : *g_scr) {
+    if (en.device == dev && en.stream == st) {
+      if (en.bytes < bytes) {
+        // the old buffer may still be read by work already queued on this stream
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        if ((e = hipFree(en.ptr)) != hipSuccess) return e;
+        en.ptr = nullptr;
+        en.bytes = 0;
+        if ((e = hipMalloc(&en.ptr, bytes)) != hipSuccess) return e;
+        en.bytes = bytes;
+      }
+      *out = en.ptr;
+      return hipSuccess;
+    }
+  }
+  void* p = nullptr;
+  if ((e = hipMalloc(&p, bytes)) != hipSuccess) return e;
+  g_scr->push_back(ScratchEntry{dev, st, p, bytes});
+  *out = p;
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -213,8 +256,9 @@ pa_status pa_forward(const pa_geometry* g, pa_dtype dtype, const void* x, void* 
   if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
   if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  PA_HIP(pa::launch_fill(dtype, y, pl.M, s), "zero y");
-  PA_HIP(pa::launch_forward_accumulate(pl, x, y, s), "forward kernel");
+  void* scratch = nullptr;
+  if (pl.fp_grid > 0) PA_HIP(get_scratch(pl.fwd_scratch, s, &scratch), "forward scratch allocation");
+  PA_HIP(pa::launch_forward(pl, x, y, scratch, nullptr, s), "forward kernels");
   return PA_OK;
 }
 

@@ -22,18 +22,6 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(T* __restrict__ p, int64_t
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = (T)0;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) norm2_kernel(const T* __restrict__ v, int64_t n, double* __restrict__ part) {
-  __shared__ double red[4];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    const double a = (double)v[i];
-    acc += a * a;
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
-}
-
 // r = y - q (q may be NULL); partial sums of ||r||^2; resets the solve state.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) init_r_kernel(T* __restrict__ r, const T* __restrict__ y, const T* __restrict__ q,
@@ -140,13 +128,6 @@ hipError_t launch_fill(pa_dtype dt, void* p, int64_t n, hipStream_t st) {
   const int g = blas_grid(n);
   if (dt == PA_F32) fill_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(p), n);
   else fill_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(p), n);
-  return hipGetLastError();
-}
-
-hipError_t launch_norm2(pa_dtype dt, const void* v, int64_t n, double* part, hipStream_t st) {
-  const int g = blas_grid(n);
-  if (dt == PA_F32) norm2_kernel<float><<<g, kBlock, 0, st>>>(static_cast<const float*>(v), n, part);
-  else norm2_kernel<double><<<g, kBlock, 0, st>>>(static_cast<const double*>(v), n, part);
   return hipGetLastError();
 }
 

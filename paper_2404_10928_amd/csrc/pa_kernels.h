@@ -21,9 +21,9 @@ struct CgArgs {
 hipError_t launch_fill(pa_dtype dt, void* p, int64_t n, hipStream_t st);
 // x := A^T y (or the CGLS epilogue when cg != nullptr)
 hipError_t launch_adjoint(const Plan& pl, const void* y, void* x, const CgArgs* cg, hipStream_t st);
-// y += A x (y must hold zeros for y := A x)
-hipError_t launch_forward_accumulate(const Plan& pl, const void* x, void* y, hipStream_t st);
-hipError_t launch_norm2(pa_dtype dt, const void* v, int64_t n, double* part, hipStream_t st);
+// y := A x in two passes through `scratch` (plan.fwd_scratch bytes); when
+// part_q is not NULL it receives plan.gather_grid FP64 partial sums of ||y||^2
+hipError_t launch_forward(const Plan& pl, const void* x, void* y, void* scratch, double* part_q, hipStream_t st);
 hipError_t launch_init_r(pa_dtype dt, void* r, const void* y, const void* q, int64_t m, double* part_r, int* status,
                          double* alpha0, hipStream_t st);
 hipError_t launch_upd_r(pa_dtype dt, void* r, const void* q, int64_t m, const double* part_q, int gq, const double* part_p,

@@ -33,8 +33,6 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
 }
 
-__device__ __forceinline__ size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
-
 // ---------------------------------------------------------------------------
 // Per (tile, sensor) constants.
 //
@@ -189,6 +187,15 @@ __device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], 
   c.act = active ? 1 : 0;
 }
 
+// FP64 sensor vector and reference of a "near" (tile, sensor) pair, used by
+// the FP32 kernels: when a sensor lies within a few tile half-diagonals of
+// the tile, R can be small against the tile-local terms of num, so the delay
+// and weight of such pairs are formed from FP64 coordinates instead.
+struct Near32 {
+  double DX, DY, DZ, KR;
+};
+static_assert(sizeof(Near32) == 32, "Near32 layout");
+
 // The per-pair arithmetic.  Returns the byte offset of tap k0 in LDS, the
 // fraction f and the tap weight in kernel units (FP32: 1 / (2R); FP64: 1 / R).
 template <int ND, bool FRAC>
@@ -208,6 +215,27 @@ __device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f,
   if (FRAC) d = d - t0f;
   f = __builtin_amdgcn_fractf(d);           // d - floor(d), exact
   kbyte = (int)floorf(d) * 4 + c.BASE;
+}
+
+// FP32 kernels, near pairs: delay and weight from FP64 coordinates.
+template <int ND, bool FRAC>
+__device__ __forceinline__ void phase_near(const Near32& n, const double o[3], double rmin2, double t0fd, int base,
+                                           float half, int& kbyte, float& f, float& wt) {
+  const double dx = o[0] + n.DX;
+  const double dy = o[1] + n.DY;
+  double R2 = dx * dx + dy * dy;
+  if (ND == 3) {
+    const double dz = o[2] + n.DZ;
+    R2 = R2 + dz * dz;
+  }
+  R2 = fmax(R2, rmin2);
+  const double R = sqrt(R2);
+  double d = R - n.KR;
+  if (FRAC) d = d - t0fd;
+  const double fl = floor(d);
+  f = (float)(d - fl);
+  wt = (float)((double)half / R);
+  kbyte = (int)fl * 4 + base;
 }
 
 template <int ND, bool FRAC>
@@ -243,6 +271,13 @@ __device__ __forceinline__ T lds_load(const T* addr) {
       static_cast<unsigned>(reinterpret_cast<size_t>(addr)));
 }
 
+template <typename T> constexpr size_t near_bytes() { return sizeof(T) == 4 ? sizeof(Near32) : 0; }
+
+__device__ __forceinline__ bool is_near(const OpParams& P, const double ref[3], const double sp[3]) {
+  const double dx = ref[0] - sp[0], dy = ref[1] - sp[1], dz = ref[2] - sp[2];
+  return dx * dx + dy * dy + dz * dz < P.near_r2;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -250,6 +285,9 @@ __device__ __forceinline__ T lds_load(const T* addr) {
 // chunks: the chunk's per-sensor constants and each sensor's trace window
 // (the samples any pixel of the tile can reach, zero outside 0..K-1) are
 // staged in LDS, then every lane gathers its two taps per sensor from LDS.
+// Within a chunk the sensors are ordered far-first (a deterministic
+// compaction), so the fast FP32 loop runs without per-sensor tests and the
+// few near sensors follow in an FP64-delay loop.
 // With CG the epilogue also performs x += alpha p, s = A^T r - lambda x and the
 // FP64 partial sums of ||s||^2 and ||x||^2.
 template <typename T, int ND, bool FRAC, bool CG>
@@ -260,17 +298,23 @@ __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restr
   using SC = typename SCOf<T>::type;
   using PX = typename PixOf<T>::type;
   constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
+  constexpr bool F32 = sizeof(T) == 4;
   extern __shared__ __align__(16) unsigned char smem[];
-  SC* sct = reinterpret_cast<SC*>(smem);
-  int* klo_s = reinterpret_cast<int*>(smem + align16((size_t)P.sc * sizeof(SC)));
-  T* win = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(klo_s) + align16((size_t)P.sc * 4));
+  const BpLayout L = bp_layout(P.sc, P.wp, sizeof(T), sizeof(SC), near_bytes<T>());
+  SC* sct = reinterpret_cast<SC*>(smem + L.sct);
+  int* klo_s = reinterpret_cast<int*>(smem + L.klo);
+  int* sid = reinterpret_cast<int*>(smem + L.sid);
+  Near32* ntab = reinterpret_cast<Near32*>(smem + L.nd);
+  T* win = reinterpret_cast<T*>(smem + L.win);
   __shared__ double red[4];
+  __shared__ int cnt[8];
 
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = tile % P.ntile[0];
   const int by = (tile / P.ntile[0]) % P.ntile[1];
   const int bz = tile / (P.ntile[0] * P.ntile[1]);
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
   const int ix = bx * TX + lx, iy = by * TY + ly, iz = bz * TZ + lz;
   const bool valid = ix < P.nx && iy < P.ny && iz < P.nz;
@@ -289,20 +333,50 @@ __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restr
   PX px;
   make_pix<ND>(P, lx, ly, lz, px);
   const float t0f = P.t0f;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
 
   T acc = 0;
   for (int s0 = 0; s0 < P.S; s0 += P.sc) {
     const int nsc = min(P.sc, P.S - s0);
-    if (tid < nsc) {
-      double sp[3];
+    const bool mine = tid < nsc;
+    double sp[3] = {0.0, 0.0, 0.0};
+    bool in_trace = false, near = false;
+    int kl = 0;
+    if (mine) {
       sensor_pos<ND>(P, s0 + tid, sp);
-      bool in_trace;
-      const int kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wp);
+      kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wp);
+      near = F32 && in_trace && is_near(P, ref, sp);
+    }
+    // far sensors first, then near ones; order within each group = sensor order
+    const unsigned long long bfar = __ballot(mine && !near);
+    const unsigned long long bnear = __ballot(mine && near);
+    if (lane == 0) {
+      cnt[wave] = __popcll(bfar);
+      cnt[4 + wave] = __popcll(bnear);
+    }
+    __syncthreads();
+    const int nfar = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    int far_before = 0, near_before = 0;
+    for (int w = 0; w < wave; ++w) {
+      far_before += cnt[w];
+      near_before += cnt[4 + w];
+    }
+    if (mine) {
+      const int pos = near ? nfar + near_before + __popcll(bnear & lt_mask) : far_before + __popcll(bfar & lt_mask);
       SC c;
-      make_sc<ND>(P, ref, sp, kl, tid * P.wp, in_trace, c);
+      make_sc<ND>(P, ref, sp, kl, pos * P.wp, in_trace, c);
       c.BASE += (int)(size_t)win;  // absolute LDS byte address of the row's reference sample
-      sct[tid] = c;
-      klo_s[tid] = in_trace ? kl : P.K + 8;  // inactive rows stage zeros
+      sct[pos] = c;
+      klo_s[pos] = in_trace ? kl : P.K + 8;  // inactive rows stage zeros
+      sid[pos] = s0 + tid;
+      if (near) {
+        Near32 n;
+        n.DX = ref[0] - sp[0];
+        n.DY = ref[1] - sp[1];
+        n.DZ = ref[2] - sp[2];
+        n.KR = rint(sqrt(n.DX * n.DX + n.DY * n.DY + n.DZ * n.DZ));
+        ntab[pos] = n;
+      }
     }
     __syncthreads();
     const int tot = nsc * P.wp;
@@ -310,7 +384,7 @@ __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restr
       const int j = (int)__umulhi((unsigned)e, P.wp_magic);
       const int k = klo_s[j] + (e - j * P.wp);
       T v = 0;
-      if (k >= 0 && k < P.K) v = y[(size_t)(s0 + j) * P.K + k];
+      if (k >= 0 && k < P.K) v = y[(size_t)sid[j] * P.K + k];
       win[e] = v;
     }
     __syncthreads();
@@ -319,7 +393,7 @@ __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restr
     // Four sensors per step: four delays, then four independent window
     // reads, then the sums in sensor order (the order never changes).
     int j = 0;
-    for (; j + 4 <= nsc; j += 4) {
+    for (; j + 4 <= nfar; j += 4) {
       int kb[4];
       T f[4], wt[4], y0[4], y1[4];
 #pragma unroll
@@ -333,7 +407,7 @@ __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restr
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc = fma(wt[u], fma(f[u], y1[u] - y0[u], y0[u]), acc);
     }
-    for (; j < nsc; ++j) {
+    for (; j < nfar; ++j) {
       int kb;
       T f, wt;
       phase<ND, FRAC>(sct[j], px, t0f, kb, f, wt);
@@ -342,11 +416,27 @@ __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restr
       const T y1 = lds_load(tap + 1);
       acc = fma(wt, fma(f, y1 - y0, y0), acc);
     }
+    if constexpr (F32) {
+      if (nfar < nsc) {
+        double o[3];
+        pix_offsets<ND>(P, lx, ly, lz, o);
+        for (; j < nsc; ++j) {
+          const SC32& c = sct[j];
+          int kb;
+          float f, wt;
+          phase_near<ND, FRAC>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, c.HALF, kb, f, wt);
+          const float* tap = reinterpret_cast<const float*>(static_cast<size_t>(kb));
+          const float y0 = lds_load(tap);
+          const float y1 = lds_load(tap + 1);
+          acc = fmaf(wt, fmaf(f, y1 - y0, y0), acc);
+        }
+      }
+    }
     __syncthreads();
   }
 
   const size_t idx = ((size_t)iz * P.ny + iy) * P.nx + ix;
-  const T scale = sizeof(T) == 4 ? (T)P.out_scale : (T)P.out_scale_d;
+  const T scale = F32 ? (T)P.out_scale : (T)P.out_scale_d;
   if (!CG) {
     if (valid) out[idx] = acc * scale;
     return;
@@ -372,24 +462,26 @@ __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restr
 }
 
 // ---------------------------------------------------------------------------
-// A: one work-group per (forward tile, chunk of 64 sensors); lane = sensor,
-// wave w walks base tiles w, w+4, ... of the forward tile one pixel at a time
-// (the pixel is uniform across the wave).  Each lane scatters its two taps
-// into its own sensor's LDS histogram row, so the lanes of one ds_add never
-// collide on an address.  The rows are then added into y with global atomics
-// (y must be zero on entry).
+// A, pass 1: one work-group per (forward tile, chunk of 64 sensors); lane =
+// sensor, wave w walks base tiles w, w+4, ... of the forward tile one pixel at
+// a time (the pixel is uniform across the wave).  Each lane scatters its two
+// taps into its own sensor's LDS histogram row, so the lanes of one ds_add
+// never collide on an address.  The rows are then written out with plain
+// coalesced stores, with the first sample of each row in a table.
 template <typename T, int ND, bool FRAC>
-__global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restrict__ x, T* __restrict__ y) {
+__global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restrict__ x, T* __restrict__ rows,
+                                                     int* __restrict__ klo_tab) {
   using SC = typename SCOf<T>::type;
   using PX = typename PixOf<T>::type;
   constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
   constexpr int NS = kSensorsPerFwdBlock;
+  constexpr bool F32 = sizeof(T) == 4;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* hist = reinterpret_cast<T*>(smem);
-  unsigned char* p1 = smem + align16((size_t)NS * P.wpa * sizeof(T));
-  PX* pixtab = reinterpret_cast<PX*>(p1);
-  T* xs = reinterpret_cast<T*>(p1 + (size_t)kBlock * sizeof(PX));
-  int* klo_a = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(xs) + align16((size_t)P.nsub * kBlock * sizeof(T)));
+  const FpLayout L = fp_layout(P.wpa, P.nsub, sizeof(T), sizeof(PX));
+  T* hist = reinterpret_cast<T*>(smem + L.hist);
+  PX* pixtab = reinterpret_cast<PX*>(smem + L.pixtab);
+  T* xs = reinterpret_cast<T*>(smem + L.xs);
+  int* klo_a = reinterpret_cast<int*>(smem + L.klo);
 
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int chunk = b % P.n_chunks;
@@ -456,39 +548,114 @@ __global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restr
     c.BASE += (int)(size_t)hist;  // absolute LDS byte address
     asm volatile("" : "+v"(c.BASE));  // keep "k * 4 + BASE" a single shift-add
     const T* xm = xs + m * kBlock;
-    for (int lz = 0; lz < nlz; ++lz) {
-      for (int ly = 0; ly < nly; ++ly) {
-        const int rowp = (lz * TY + ly) * TX;
+    const bool near = F32 && active && is_near(P, ref, sp);
+    if (__ballot(near) == 0) {
+      for (int lz = 0; lz < nlz; ++lz) {
+        for (int ly = 0; ly < nly; ++ly) {
+          const int rowp = (lz * TY + ly) * TX;
 #pragma unroll 2
-        for (int lx = 0; lx < nlx; ++lx) {
-          const PX px = pixtab[rowp + lx];
-          const T xp = xm[rowp + lx];
-          int kb;
-          T f, wt;
-          phase<ND, FRAC>(c, px, t0f, kb, f, wt);
-          const T v = wt * xp;
-          const T a1 = v * f;
-          const T a0 = v - a1;
-          T* bin = reinterpret_cast<T*>(static_cast<size_t>(kb));
-          lds_add(bin, a0);
-          lds_add(bin + 1, a1);
+          for (int lx = 0; lx < nlx; ++lx) {
+            const PX px = pixtab[rowp + lx];
+            const T xp = xm[rowp + lx];
+            int kb;
+            T f, wt;
+            phase<ND, FRAC>(c, px, t0f, kb, f, wt);
+            const T v = wt * xp;
+            const T a1 = v * f;
+            const T a0 = v - a1;
+            T* bin = reinterpret_cast<T*>(static_cast<size_t>(kb));
+            lds_add(bin, a0);
+            lds_add(bin + 1, a1);
+          }
+        }
+      }
+    } else if constexpr (F32) {
+      // some lane's sensor is near this tile: those lanes take the FP64 delay
+      Near32 nn;
+      nn.DX = ref[0] - sp[0];
+      nn.DY = ref[1] - sp[1];
+      nn.DZ = ref[2] - sp[2];
+      nn.KR = rint(sqrt(nn.DX * nn.DX + nn.DY * nn.DY + nn.DZ * nn.DZ));
+      const double rmin2 = P.rmin * P.rmin;
+      for (int lz = 0; lz < nlz; ++lz) {
+        for (int ly = 0; ly < nly; ++ly) {
+          const int rowp = (lz * TY + ly) * TX;
+          for (int lx = 0; lx < nlx; ++lx) {
+            const Pix32 px = pixtab[rowp + lx];
+            const float xp = xm[rowp + lx];
+            int kb;
+            float f, wt;
+            if (near) {
+              double o[3];
+              pix_offsets<ND>(P, lx, ly, lz, o);
+              phase_near<ND, FRAC>(nn, o, rmin2, P.t0fd, c.BASE, c.HALF, kb, f, wt);
+            } else {
+              phase<ND, FRAC>(c, px, t0f, kb, f, wt);
+            }
+            const float v = wt * xp;
+            const float a1 = v * f;
+            const float a0 = v - a1;
+            float* bin = reinterpret_cast<float*>(static_cast<size_t>(kb));
+            lds_add(bin, a0);
+            lds_add(bin + 1, a1);
+          }
         }
       }
     }
   }
   __syncthreads();
 
-  const T scale = sizeof(T) == 4 ? (T)P.out_scale : (T)P.out_scale_d;
+  // histogram rows out, row (forward tile, sensor) at ((at * S) + s) * wpa
   for (int j = wave; j < NS; j += 4) {
     const int sj = chunk * NS + j;
     if (sj >= P.S) break;
-    const int k0 = klo_a[j];
-    T* row = y + (size_t)sj * P.K;
-    for (int i = lane; i < P.wpa; i += 64) {
-      const int k = k0 + i;
-      const T v = hist[j * P.wpa + i];
-      if (v != (T)0 && k >= 0 && k < P.K) unsafeAtomicAdd(row + k, v * scale);
-    }
+    T* row = rows + ((size_t)at * P.S + sj) * P.wpa;
+    for (int i = lane; i < P.wpa; i += 64) row[i] = hist[j * P.wpa + i];
+  }
+  if (wave == 0 && s_ok) klo_tab[(size_t)at * P.S + s] = klo_a[lane];
+}
+
+// A, pass 2: one work-group per (sensor, segment of kseg samples).  Wave w
+// adds the rows of forward tiles w, w+4, ... (in increasing order) into its
+// own LDS copy of the segment; the four copies are then summed in a fixed
+// order, scaled and written to y, with the FP64 partial of ||y||^2.  No
+// atomics: the result is the same on every run.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fp_gather_kernel(OpParams P, const T* __restrict__ rows,
+                                                            const int* __restrict__ klo_tab, T* __restrict__ y,
+                                                            double* __restrict__ part_q) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* tr = reinterpret_cast<T*>(smem);
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int s = blockIdx.x / P.nseg;
+  const int seg = blockIdx.x - s * P.nseg;
+  const int k0 = seg * P.kseg;
+  const int kn = min(P.kseg, P.K - k0);
+  for (int i = tid; i < 4 * P.kseg; i += kBlock) tr[i] = 0;
+  __syncthreads();
+  T* mine = tr + wave * P.kseg;
+  for (int at = wave; at < P.n_atiles; at += 4) {
+    const int kl = __builtin_amdgcn_readfirstlane(klo_tab[(size_t)at * P.S + s]);
+    const int lo = max(kl, k0), hi = min(kl + P.wpa, k0 + kn);
+    if (lo >= hi) continue;
+    const T* row = rows + ((size_t)at * P.S + s) * P.wpa;
+    for (int k = lo + lane; k < hi; k += 64) mine[k - k0] += row[k - kl];
+  }
+  __syncthreads();
+  const T scale = sizeof(T) == 4 ? (T)P.out_scale : (T)P.out_scale_d;
+  double acc = 0.0;
+  T* yrow = y + (size_t)s * P.K + k0;
+  for (int i = tid; i < kn; i += kBlock) {
+    const T v = (((tr[i] + tr[P.kseg + i]) + tr[2 * P.kseg + i]) + tr[3 * P.kseg + i]) * scale;
+    yrow[i] = v;
+    acc += (double)v * (double)v;
+  }
+  if (part_q) {
+    acc = block_sum(acc, red);
+    if (tid == 0) part_q[blockIdx.x] = acc;
   }
 }
 
@@ -497,15 +664,24 @@ __global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restr
 
 namespace {
 
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
 template <typename T, int ND, bool FRAC, bool CG>
 hipError_t launch_bp_t(const Plan& pl, const T* y, T* out, const CgArgs* cg, hipStream_t st) {
   const OpParams& P = pl.op;
+  auto kern = bp_kernel<T, ND, FRAC, CG>;
+  hipError_t e = allow_lds(kern, pl.bp_lds);
+  if (e != hipSuccess) return e;
   if (CG)
-    bp_kernel<T, ND, FRAC, CG><<<pl.bp_grid, kBlock, pl.bp_lds, st>>>(
-        P, y, out, static_cast<T*>(cg->x), static_cast<const T*>(cg->p), cg->alpha, cg->lambda, cg->part_s, cg->part_x);
+    kern<<<pl.bp_grid, kBlock, pl.bp_lds, st>>>(P, y, out, static_cast<T*>(cg->x), static_cast<const T*>(cg->p),
+                                               cg->alpha, cg->lambda, cg->part_s, cg->part_x);
   else
-    bp_kernel<T, ND, FRAC, CG><<<pl.bp_grid, kBlock, pl.bp_lds, st>>>(P, y, out, nullptr, nullptr, nullptr, 0.0,
-                                                                      nullptr, nullptr);
+    kern<<<pl.bp_grid, kBlock, pl.bp_lds, st>>>(P, y, out, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -516,14 +692,31 @@ hipError_t launch_bp_f(const Plan& pl, const T* y, T* out, const CgArgs* cg, hip
 }
 
 template <typename T, int ND, bool FRAC>
-hipError_t launch_fp_t(const Plan& pl, const T* x, T* y, hipStream_t st) {
-  fp_kernel<T, ND, FRAC><<<pl.fp_grid, kBlock, pl.fp_lds, st>>>(pl.op, x, y);
+hipError_t launch_fp_t(const Plan& pl, const T* x, T* rows, int* klo_tab, hipStream_t st) {
+  auto kern = fp_kernel<T, ND, FRAC>;
+  hipError_t e = allow_lds(kern, pl.fp_lds);
+  if (e != hipSuccess) return e;
+  kern<<<pl.fp_grid, kBlock, pl.fp_lds, st>>>(pl.op, x, rows, klo_tab);
   return hipGetLastError();
 }
 
 template <typename T, int ND>
-hipError_t launch_fp_f(const Plan& pl, const T* x, T* y, hipStream_t st) {
-  return pl.op.t0f != 0.0f ? launch_fp_t<T, ND, true>(pl, x, y, st) : launch_fp_t<T, ND, false>(pl, x, y, st);
+hipError_t launch_fp_f(const Plan& pl, const T* x, T* rows, int* klo_tab, hipStream_t st) {
+  return pl.op.t0f != 0.0f ? launch_fp_t<T, ND, true>(pl, x, rows, klo_tab, st)
+                           : launch_fp_t<T, ND, false>(pl, x, rows, klo_tab, st);
+}
+
+template <typename T>
+hipError_t launch_forward_t(const Plan& pl, const T* x, T* y, void* scratch, double* part_q, hipStream_t st) {
+  unsigned char* sc = static_cast<unsigned char*>(scratch);
+  T* rows = reinterpret_cast<T*>(sc + pl.part_rows_off);
+  int* tab = reinterpret_cast<int*>(sc + pl.klo_tab_off);
+  hipError_t e = pl.ndim == 2 ? launch_fp_f<T, 2>(pl, x, rows, tab, st) : launch_fp_f<T, 3>(pl, x, rows, tab, st);
+  if (e != hipSuccess) return e;
+  auto g = fp_gather_kernel<T>;
+  if ((e = allow_lds(g, pl.gather_lds)) != hipSuccess) return e;
+  g<<<pl.gather_grid, kBlock, pl.gather_lds, st>>>(pl.op, rows, tab, y, part_q);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -543,16 +736,16 @@ hipError_t launch_adjoint(const Plan& pl, const void* y, void* x, const CgArgs* 
   return CGm ? launch_bp_f<double, 3, true>(pl, yy, xx, cg, st) : launch_bp_f<double, 3, false>(pl, yy, xx, cg, st);
 }
 
-hipError_t launch_forward_accumulate(const Plan& pl, const void* x, void* y, hipStream_t st) {
-  if (pl.fp_grid == 0) return hipSuccess;
-  if (pl.dtype == PA_F32) {
-    auto xx = static_cast<const float*>(x);
-    auto yy = static_cast<float*>(y);
-    return pl.ndim == 2 ? launch_fp_f<float, 2>(pl, xx, yy, st) : launch_fp_f<float, 3>(pl, xx, yy, st);
+hipError_t launch_forward(const Plan& pl, const void* x, void* y, void* scratch, double* part_q, hipStream_t st) {
+  if (pl.fp_grid == 0) {
+    // nothing to scatter: y = 0, ||y||^2 = 0
+    hipError_t e = launch_fill(pl.dtype, y, pl.M, st);
+    if (e != hipSuccess || !part_q) return e;
+    return launch_fill(PA_F64, part_q, 1, st);
   }
-  auto xx = static_cast<const double*>(x);
-  auto yy = static_cast<double*>(y);
-  return pl.ndim == 2 ? launch_fp_f<double, 2>(pl, xx, yy, st) : launch_fp_f<double, 3>(pl, xx, yy, st);
+  if (pl.dtype == PA_F32)
+    return launch_forward_t<float>(pl, static_cast<const float*>(x), static_cast<float*>(y), scratch, part_q, st);
+  return launch_forward_t<double>(pl, static_cast<const double*>(x), static_cast<double*>(y), scratch, part_q, st);
 }
 
 }  // namespace pa

@@ -101,7 +101,20 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   op.n_tiles = op.ntile[0] * op.ntile[1] * op.ntile[2];
 
   const size_t elem = pl.elem;
-  const size_t sc_bytes = dtype == PA_F32 ? 48 : 64;  // per-sensor constants in LDS (adjoint)
+  const bool f32 = dtype == PA_F32;
+  const size_t sc_bytes = f32 ? 48 : 64;     // per-sensor constants in LDS (adjoint)
+  const size_t near_bytes = f32 ? 32 : 0;    // FP64 sensor vector + reference (FP32 near path)
+  const size_t pix_bytes = f32 ? 16 : 32;
+
+  // Sensors closer than three base-tile half-diagonals to a tile centre take
+  // the FP64 delay path in the FP32 kernels (the tile-local FP32 form loses
+  // relative precision in R^2 when R is small against the tile size).
+  {
+    double ex = (TX - 1) * hs, ey = (TY - 1) * hs, ez = (TZ - 1) * hs;
+    double hd = 0.5 * std::sqrt(ex * ex + ey * ey + ez * ez);
+    double nr = 3.0 * hd + 2.0;
+    op.near_r2 = nr * nr;
+  }
 
   // Adjoint: window of one sensor over the base tile's pixel-centre box.  Any
   // two pixels of the box differ in distance by at most its diagonal; the
@@ -111,46 +124,63 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
     if (diag > 1e6) return fail(msg, PA_ERR_UNSUPPORTED, "pixel pitch spans too many samples");
     op.wp = (int32_t)std::ceil(diag) + 5;
-    size_t per = sc_bytes + 4 + (size_t)op.wp * elem;
-    int64_t sc_max = (int64_t)(40 * 1024 / per);
-    if (sc_max < 1) sc_max = (int64_t)(kLdsBudget / per);
+    const size_t per = sc_bytes + 8 + near_bytes + (size_t)op.wp * elem;
+    const size_t slack = 64;  // alignment of the four LDS arrays
+    int64_t sc_max = (int64_t)((40 * 1024 - slack) / per);
+    if (sc_max < 1) sc_max = (int64_t)((kLdsPreferred - slack) / per);
+    if (sc_max < 1) sc_max = (int64_t)((kLdsMax - slack) / per);
     if (sc_max < 1) return fail(msg, PA_ERR_UNSUPPORTED, "trace window of one tile does not fit in LDS (h / (c dt) too large)");
     sc_max = std::min<int64_t>(sc_max, kBlock);
     int64_t S = std::max<int64_t>(g->n_sensors, 1);
     int64_t nchunk = (S + sc_max - 1) / sc_max;
     op.sc = (int32_t)((S + nchunk - 1) / nchunk);
     op.wp_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)op.wp + 1);
-    pl.bp_lds = align_up((size_t)op.sc * sc_bytes, 16) + align_up((size_t)op.sc * 4, 16) +
-                (size_t)op.sc * op.wp * elem;
+    pl.bp_lds = bp_layout(op.sc, op.wp, elem, sc_bytes, near_bytes).total;
+    if (pl.bp_lds > kLdsMax) return fail(msg, PA_ERR_UNSUPPORTED, "adjoint LDS plan exceeds 160 KiB");
   }
 
   // Forward: histogram window of one sensor over a forward tile made of
-  // msub base tiles; shrink to a single base tile if it does not fit.
+  // msub base tiles.  Prefer the largest forward tile (fewest partial rows)
+  // whose LDS keeps several work-groups per CU; else the largest that fits.
   {
-    int cand[2][3] = {{2, 2, 1}, {1, 1, 1}};
-    if (nd == 3) { cand[0][0] = 2; cand[0][1] = 1; cand[0][2] = 2; }
+    int cand2[2][3] = {{2, 2, 1}, {1, 1, 1}};
+    int cand3[4][3] = {{2, 2, 4}, {2, 2, 2}, {2, 1, 2}, {1, 1, 1}};
+    int (*cand)[3] = nd == 2 ? cand2 : cand3;
+    const int ncand = nd == 2 ? 2 : 4;
     bool ok = false;
-    for (auto& m : cand) {
-      double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
-      double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
-      int32_t wpa = ((int32_t)std::ceil(diag) + 5) | 1;  // odd stride spreads lanes over LDS banks
-      int nsub = m[0] * m[1] * m[2];
-      size_t lds = align_up((size_t)kSensorsPerFwdBlock * wpa * elem, 16) +
-                   (size_t)kBlock * (dtype == PA_F32 ? 16 : 32) +
-                   align_up((size_t)nsub * kBlock * elem, 16) + kSensorsPerFwdBlock * 4;
-      if (lds <= kLdsBudget) {
-        for (int a = 0; a < 3; ++a) op.msub[a] = m[a];
-        op.nsub = nsub;
-        op.wpa = wpa;
-        pl.fp_lds = lds;
-        ok = true;
-        break;
+    for (size_t budget : {kLdsPreferred, kLdsMax}) {
+      for (int ci = 0; ci < ncand && !ok; ++ci) {
+        int* m = cand[ci];
+        double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
+        double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
+        if (diag > 1e6) continue;
+        int32_t wpa = ((int32_t)std::ceil(diag) + 5) | 1;  // odd stride spreads lanes over LDS banks
+        int nsub = m[0] * m[1] * m[2];
+        size_t lds = fp_layout(wpa, nsub, elem, pix_bytes).total;
+        if (lds <= budget) {
+          for (int a = 0; a < 3; ++a) op.msub[a] = m[a];
+          op.nsub = nsub;
+          op.wpa = wpa;
+          pl.fp_lds = lds;
+          ok = true;
+        }
       }
+      if (ok) break;
     }
     if (!ok) return fail(msg, PA_ERR_UNSUPPORTED, "histogram window of one tile does not fit in LDS (h / (c dt) too large)");
     for (int a = 0; a < 3; ++a) op.natile[a] = ceil_div(op.ntile[a], op.msub[a]);
     op.n_atiles = op.natile[0] * op.natile[1] * op.natile[2];
     op.n_chunks = ceil_div(g->n_sensors, kSensorsPerFwdBlock);
+    // gather of the partial rows: one work-group per (sensor, segment of kseg samples)
+    op.kseg = std::max(1, std::min<int32_t>(g->n_samples, 1024));
+    op.nseg = g->n_samples > 0 ? ceil_div(g->n_samples, op.kseg) : 0;
+    pl.gather_lds = gather_lds(op.kseg, elem);
+    const size_t rows = (size_t)op.n_atiles * (size_t)g->n_sensors * (size_t)op.wpa * elem;
+    const size_t tab = (size_t)op.n_atiles * (size_t)g->n_sensors * 4;
+    pl.part_rows_off = 0;
+    pl.klo_tab_off = align_up(rows, 256);
+    pl.fwd_scratch = align_up(pl.klo_tab_off + tab, 256);
+    if (pl.fwd_scratch > ((size_t)1 << 40)) return fail(msg, PA_ERR_UNSUPPORTED, "forward scratch above 1 TiB");
   }
 
   op.out_scale = (float)(2.0 * inv_cdt);   // float path accumulates w / 2
@@ -161,12 +191,14 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   const bool empty = P == 0 || g->n_sensors == 0 || g->n_samples == 0;
   pl.bp_grid = P == 0 ? 0 : op.n_tiles;
   pl.fp_grid = empty ? 0 : op.n_atiles * op.n_chunks;
+  pl.gather_grid = empty ? 0 : g->n_sensors * op.nseg;
   return PA_OK;
 }
 
 CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   CglsLayout L{};
   const size_t A = 256;
+  L.g_q = std::max(plan.gather_grid, 1);
   L.g_m = blas_grid(plan.M);
   L.g_p = blas_grid(plan.P);
   L.g_bp = std::max(plan.op.n_tiles, 1);
@@ -174,7 +206,7 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   L.status = off; off = align_up(off + 64, A);
   L.gamma = off; off = align_up(off + sizeof(double) * (size_t)(iters + 2), A);
   L.alpha = off; off = align_up(off + sizeof(double) * (size_t)(iters + 2), A);
-  L.part_q = off; off = align_up(off + sizeof(double) * L.g_m, A);
+  L.part_q = off; off = align_up(off + sizeof(double) * L.g_q, A);
   L.part_r = off; off = align_up(off + sizeof(double) * L.g_m, A);
   L.part_s = off; off = align_up(off + sizeof(double) * L.g_bp, A);
   L.part_x = off; off = align_up(off + sizeof(double) * L.g_bp, A);
@@ -183,6 +215,7 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
   L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.vec_p = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.fwd = off; off = align_up(off + std::max<size_t>(plan.fwd_scratch, 256), A);
   L.total = off;
   return L;
 }

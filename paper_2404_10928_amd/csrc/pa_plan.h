@@ -10,7 +10,15 @@
 
 #include "pa.h"
 
+#ifdef __HIPCC__
+#define PA_HD __host__ __device__
+#else
+#define PA_HD
+#endif
+
 namespace pa {
+
+PA_HD inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
 // Base tiles: one work-group of 256 lanes, one pixel per lane.
 //   2D: 16 x 16 x 1      3D: 8 x 8 x 4
@@ -20,7 +28,8 @@ template <> struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4; };
 
 constexpr int kBlock = 256;          // lanes per work-group, every kernel
 constexpr int kSensorsPerFwdBlock = 64;  // forward operator: one sensor per lane of a wave
-constexpr size_t kLdsBudget = 64 * 1024 - 256;  // dynamic LDS per work-group (static LDS rides on top)
+constexpr size_t kLdsPreferred = 64 * 1024 - 256;  // dynamic LDS that keeps several work-groups per CU
+constexpr size_t kLdsMax = 160 * 1024 - 1024;      // gfx950: 160 KiB of LDS per work-group, minus static use
 
 // Everything a kernel needs about the operator, by value.  Lengths are in
 // "sample units": metres multiplied by 1 / (c dt), so a distance equals its
@@ -47,9 +56,46 @@ struct OpParams {
   int32_t n_atiles;
   int32_t n_chunks;         // forward: sensor chunks of 64
   int32_t wpa;              // forward: LDS histogram stride of one sensor
+  int32_t kseg;             // forward gather: samples per work-group
+  int32_t nseg;             // forward gather: segments per trace
+  double near_r2;           // squared tile-centre distance (sample units) below which a
+                            // sensor takes the FP64 delay path in the FP32 kernels
   float out_scale;          // converts accumulated kernel units to 1/metres (float path)
   double out_scale_d;       // same, double path
 };
+
+// LDS layouts, shared by the planner (sizes) and the kernels (offsets).
+struct BpLayout {
+  size_t sct, klo, sid, nd, win, total;
+};
+// sc sensors per chunk, wp samples per window row, elem bytes per sample;
+// sc_bytes per-sensor constants; near_bytes per-sensor FP64 table (0 in FP64 kernels).
+PA_HD inline BpLayout bp_layout(int sc, int wp, size_t elem, size_t sc_bytes, size_t near_bytes) {
+  BpLayout L;
+  L.sct = 0;
+  L.klo = align16((size_t)sc * sc_bytes);
+  L.sid = L.klo + align16((size_t)sc * 4);
+  L.nd = L.sid + align16((size_t)sc * 4);
+  L.win = L.nd + align16((size_t)sc * near_bytes);
+  L.total = L.win + (size_t)sc * wp * elem;
+  return L;
+}
+
+struct FpLayout {
+  size_t hist, pixtab, xs, klo, total;
+};
+PA_HD inline FpLayout fp_layout(int wpa, int nsub, size_t elem, size_t pix_bytes) {
+  FpLayout L;
+  L.hist = 0;
+  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * elem);
+  L.xs = L.pixtab + (size_t)kBlock * pix_bytes;
+  L.klo = L.xs + align16((size_t)nsub * kBlock * elem);
+  L.total = L.klo + kSensorsPerFwdBlock * 4;
+  return L;
+}
+
+// forward gather: one private copy of the trace segment per wave
+PA_HD inline size_t gather_lds(int kseg, size_t elem) { return 4 * (size_t)kseg * elem; }
 
 struct Plan {
   OpParams op;
@@ -57,8 +103,10 @@ struct Plan {
   pa_dtype dtype;
   size_t elem;              // sizeof(T)
   int64_t P, M;             // pixels, samples (S*K)
-  size_t bp_lds, fp_lds;    // dynamic LDS bytes
-  int bp_grid, fp_grid;
+  size_t bp_lds, fp_lds, gather_lds;  // dynamic LDS bytes
+  int bp_grid, fp_grid, gather_grid;
+  size_t fwd_scratch;       // bytes of forward-operator scratch (partial rows + window table)
+  size_t part_rows_off, klo_tab_off;  // offsets inside that scratch
 };
 
 // Fills *plan from g.  Returns PA_OK or an error with *msg set.  Never touches
@@ -71,8 +119,8 @@ int blas_grid(int64_t n);
 
 // CGLS workspace layout.
 struct CglsLayout {
-  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, total;
-  int g_m, g_p, g_bp;       // partial counts: over S*K, over pixels, adjoint tiles
+  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, fwd, total;
+  int g_q, g_m, g_p, g_bp;  // partial counts: forward gather, over S*K, over pixels, adjoint tiles
 };
 CglsLayout cgls_layout(const Plan& plan, int32_t iters);
 

@@ -31,6 +31,11 @@ class Workload:
     def geom(self) -> Geometry:
         return self.geoms[0]
 
+    @property
+    def x(self) -> np.ndarray:
+        """Phantom of the first (for single-frame workloads, the only) frame."""
+        return self.x_true[0]
+
 
 def _c1(seed_base=1001):
     n, h = 128, 1e-4

@@ -181,7 +181,7 @@ def test_c1_full(pa):
 def test_c2_full(pa):
     w = make_config("C2")
     g = w.geom
-    x = w.x_true
+    x = w.x
     xg, x64 = rounded(x, np.float32)
     y_ref = oracle.forward(g, x64)
     yf = run_forward(pa, g, xg, np.float32)
@@ -197,7 +197,7 @@ def test_c5_sampled(pa):
     """128^3 voxels x 1024 sensors: compare outputs the oracle computes one by one."""
     w = make_config("C5")
     g = w.geom
-    xg, x64 = rounded(w.x_true, np.float32)
+    xg, x64 = rounded(w.x, np.float32)
     y = run_forward(pa, g, xg, np.float32)
     rng = np.random.default_rng(5005)
     # sample where the signal is: 24 random sensors, 4 samples each around its arrival peak

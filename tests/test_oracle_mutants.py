@@ -27,6 +27,9 @@ MUTANTS = {
                          "for (int64_t i = 0; i < P; ++i) s[i] += lambda * x[i];\n    double gamma1"),
     "clamp_full_pitch": ("return g->r_min > 0 ? g->r_min : 0.5 * g->h;", "return g->r_min > 0 ? g->r_min : g->h;"),
     "landweber_step_sign": ("x[i] += omega * (s[i] - lambda * x[i]);", "x[i] += omega * (s[i] + lambda * x[i]);"),
+    "tv_gradient_lost_term": ("          grad[p] -= dy / m;\n", ""),
+    "tv_vertical_difference": ("const double dy = iy + 1 < ny ? x[p + nx] - x[p] : 0.0;",
+                               "const double dy = iy + 1 < ny ? x[p + 1] - x[p] : 0.0;"),
 }
 
 PINS = [
@@ -40,6 +43,8 @@ PINS = [
     lambda: pins.test_cgls_reaches_regularised_normal_equations(1e-2),
     pins.test_cgls_iterates_minimise_over_krylov_spaces,
     pins.test_landweber_closed_form,
+    pins.test_tv_closed_forms,
+    pins.test_tv_gradient_matches_finite_differences_and_shift_invariance,
 ]
 
 

@@ -274,3 +274,56 @@ def test_landweber_closed_form():
     x_ref = sum(np.linalg.matrix_power(T, j) @ (omega * b) for j in range(k))
     np.testing.assert_allclose(x.reshape(-1), x_ref, rtol=1e-10, atol=1e-12 * np.abs(x_ref).max())
     assert np.all(np.diff(hist) <= 1e-12 * hist[0])
+
+
+# --------------------------------------------------------------------------
+# total variation term (Eq. 8) and the loss gradient
+
+def test_tv_closed_forms():
+    eps = 1e-3
+    ny, nx = 6, 9
+    assert oracle.tv2d(np.full((ny, nx), 3.7), eps)[0] == pytest.approx(nx * ny * eps, rel=1e-14)
+    a, b = 0.7, -0.4
+    iy, ix = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    v, g = oracle.tv2d(a * ix + b * iy, eps)
+    expect = ((nx - 1) * (ny - 1) * math.sqrt(a * a + b * b + eps * eps) + (ny - 1) * math.sqrt(b * b + eps * eps)
+              + (nx - 1) * math.sqrt(a * a + eps * eps) + eps)
+    assert v == pytest.approx(expect, rel=1e-13)
+    # a plane has zero TV gradient away from the borders
+    np.testing.assert_allclose(g[1:-1, 1:-1], 0.0, atol=1e-12)
+
+
+def test_tv_gradient_matches_finite_differences_and_shift_invariance():
+    rng = np.random.default_rng(17)
+    x = rng.uniform(size=(7, 8))
+    eps = 1e-2
+    v, g = oracle.tv2d(x, eps)
+    h = 1e-6
+    for p in rng.choice(x.size, 20, replace=False):
+        e = np.zeros(x.size)
+        e[p] = h
+        e = e.reshape(x.shape)
+        fd = (oracle.tv2d(x + e, eps)[0] - oracle.tv2d(x - e, eps)[0]) / (2 * h)
+        assert g.reshape(-1)[p] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    assert oracle.tv2d(x + 5.0, eps)[0] == pytest.approx(v, rel=1e-12)
+    assert abs(g.sum()) < 1e-10
+
+
+def test_loss_gradient_is_exact_for_the_quadratic_term():
+    g, y = tiny_problem(6)
+    rng = np.random.default_rng(8)
+    x = rng.uniform(size=g.image_shape)
+    val, grad = oracle.loss_gradient(g, x, y, tv_weight=0.0)
+    A = dense(g)
+    np.testing.assert_allclose(grad.reshape(-1), 2 * A.T @ (A @ x.reshape(-1) - y.reshape(-1)), rtol=1e-10,
+                               atol=1e-10 * np.abs(grad).max())
+    # central differences are exact for a quadratic (up to rounding)
+    val_t, grad_t = oracle.loss_gradient(g, x, y, tv_weight=1e-3, eps=1e-2)
+    h = 1e-3
+    for p in rng.choice(x.size, 10, replace=False):
+        e = np.zeros(x.size)
+        e[p] = h
+        e = e.reshape(x.shape)
+        fp = oracle.loss_gradient(g, x + e, y, 1e-3, 1e-2)[0]
+        fm = oracle.loss_gradient(g, x - e, y, 1e-3, 1e-2)[0]
+        assert grad_t.reshape(-1)[p] == pytest.approx((fp - fm) / (2 * h), rel=1e-5, abs=1e-6 * np.abs(grad_t).max())
