@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle CGLS iterations timed on the host")
     ap.add_argument("--quick", action="store_true", help="skip operator and CPU legs (profiling runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=64,
+                    help="size of a plain device copy run once (counter calibration for profiling runs)")
     return ap.parse_args()
 
 
@@ -79,6 +81,14 @@ def main():
     y = torch.from_numpy(y_np.astype(np.float32)).to(dev)
     torch.cuda.synchronize()
     print(f"[bench] workload ready: P={P} S={S} K={K}", file=sys.stderr, flush=True)
+
+    # a plain copy of known size: HBM-counter calibration for profiling runs
+    if args.calib_copy_mib > 0:
+        a = torch.empty(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # ------------------------------------------------------------ CGLS steps
     solver = pa.CglsSolver(geom, torch.float32, w.iters, w.lam, graph=True, device=dev)

@@ -33,4 +33,56 @@ hipError_t launch_dir(pa_dtype dt, void* p, const void* s, int64_t np, void* q, 
                       const double* part_x, int gx, const double* part_r, int gr, double lambda, double* gamma, int k,
                       const int* status, double* hist, double* part_p, hipStream_t st);
 
+// ------------------------------------------------------------------ batches
+
+// Index of the frame whose block range of one batched launch contains global
+// block g (ranges are consecutive in table order; empty ranges are skipped
+// because they share their start with the next frame).
+template <int32_t FrameDesc::*BEG>
+__device__ __forceinline__ int find_frame(const FrameDesc* __restrict__ B, int nf, int g) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (B[mid].*BEG <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// What a batched launch needs: the device frame table and the totals.
+struct BatchLaunch {
+  const FrameDesc* table;   // device, nf entries
+  int nf;
+  pa_dtype dtype;
+  int ndim;
+  bool frac;                // some frame has a fractional t0 / dt
+  unsigned char* scratch;   // device forward scratch area
+  int bp_grid, fp_grid, gather_grid, m_grid, p_grid;
+  size_t bp_lds, fp_lds, gather_lds;
+  int64_t P_total, M_total;
+};
+
+// CGLS epilogue of the batched adjoint: per-frame alpha at
+// alpha[frame * astride + acol].
+struct BatchCg {
+  void* x;
+  const void* p;
+  const double* alpha;
+  int astride, acol;
+  double lambda;
+  double* part_s;
+  double* part_x;
+};
+
+hipError_t launch_adjoint_batched(const BatchLaunch& L, const void* y, void* x, const BatchCg* cg, hipStream_t st);
+hipError_t launch_forward_batched(const BatchLaunch& L, const void* x, void* y, double* part_q, hipStream_t st);
+hipError_t launch_init_r_batched(const BatchLaunch& L, void* r, const void* y, const void* q, double* part_r,
+                                 int* status, double* alpha, int astride, hipStream_t st);
+hipError_t launch_upd_r_batched(const BatchLaunch& L, void* r, const void* q, const double* part_q,
+                                const double* part_p, double lambda, const double* gamma, double* alpha, int astride,
+                                int* status, int k, double* part_r, hipStream_t st);
+hipError_t launch_dir_batched(const BatchLaunch& L, void* p, const void* s, const double* part_s, const double* part_x,
+                              const double* part_r, double lambda, double* gamma, int astride, int k,
+                              const int* status, double* hist, int hstride, double* part_p, hipStream_t st);
+
 }  // namespace pa

@@ -1,0 +1,661 @@
+// Device code of the operator kernels: per-pair delay arithmetic, LDS
+// layouts and the kernel bodies, shared by the single-frame kernels
+// (pa_ops.hip) and the batched kernels (pa_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pa_device.h"
+#include "pa_plan.h"
+
+namespace pa {
+
+namespace {
+
+using dev::block_sum;
+
+
+constexpr float kInactiveCmin = 1.0f;
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // Work-groups are dealt round-robin to the 8 XCDs (block b -> XCD b % 8).
+  // Give each XCD a contiguous run of tiles so neighbouring tiles, which read
+  // overlapping trace windows, share one L2.
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + idx;
+}
+
+// ---------------------------------------------------------------------------
+// Per (tile, sensor) constants.
+//
+// FP32 path ("tile-local delay").  tau ~ 2000 samples has an FP32 spacing of
+// 1.2e-4, too coarse for the interpolation fraction.  Instead each (tile,
+// sensor) pair gets, in FP64, the sensor-to-tile-centre vector D (sample
+// units) and an integer reference kr = round(|D|).  For a pixel at offset o
+// from the tile centre,
+//   num = R^2 - kr^2 = (|D|^2 - kr^2) + 2 D.o + |o|^2
+// is formed in FP32 from small terms, and R - kr follows from one Newton step
+// on d (d + 2 kr) = num starting at the FP32 estimate R^2 * rsq(R^2) - kr.
+// The result is accurate to ~1e-6 samples.
+struct SC32 {
+  float E;      // |D|^2 - kr^2
+  float DX2, DY2, DZ2;  // 2 D
+  float KRN;    // -kr
+  float KR2N;   // -2 kr
+  float KR2;    // kr^2
+  float CMIN;   // rmin^2 - kr^2 (distance clamp, in num units)
+  int BASE;     // byte offset of sample (kr - t0i) in this sensor's LDS row
+  int act;      // 0: sensor contributes nothing to this tile
+  float HALF;   // 0.5 (active) or 0 (inactive): weight multiplier
+  int pad;
+};
+static_assert(sizeof(SC32) == 48, "SC32 layout");
+
+// FP64 path: plain distance arithmetic in double.
+struct SC64 {
+  double DX, DY, DZ;  // D
+  double KR;          // kr
+  double RMIN2;       // rmin^2
+  double ACT;         // 1 or 0: weight multiplier
+  double T0F;         // t0 / dt - floor(t0 / dt)
+  int BASE;           // byte offset of sample (kr - t0i) in this sensor's LDS row
+  int act;
+};
+static_assert(sizeof(SC64) == 64, "SC64 layout");
+
+template <typename T> struct SCOf;
+template <> struct SCOf<float> { using type = SC32; };
+template <> struct SCOf<double> { using type = SC64; };
+
+// Offsets of one pixel of a base tile from the tile centre, sample units.
+struct Pix32 { float ox, oy, oz, q; };
+struct Pix64 { double ox, oy, oz, pad; };
+template <typename T> struct PixOf;
+template <> struct PixOf<float> { using type = Pix32; };
+template <> struct PixOf<double> { using type = Pix64; };
+
+template <int ND>
+__device__ __forceinline__ void pix_offsets(const OpParams& P, int lx, int ly, int lz, double o[3]) {
+  o[0] = ((double)lx - 0.5 * (Tile<ND>::X - 1)) * P.hs;
+  o[1] = ((double)ly - 0.5 * (Tile<ND>::Y - 1)) * P.hs;
+  o[2] = ND == 3 ? ((double)lz - 0.5 * (Tile<ND>::Z - 1)) * P.hs : 0.0;
+}
+
+template <int ND>
+__device__ __forceinline__ void make_pix(const OpParams& P, int lx, int ly, int lz, Pix32& p) {
+  double o[3];
+  pix_offsets<ND>(P, lx, ly, lz, o);
+  p.ox = (float)o[0];
+  p.oy = (float)o[1];
+  p.oz = (float)o[2];
+  p.q = (float)(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+}
+
+template <int ND>
+__device__ __forceinline__ void make_pix(const OpParams& P, int lx, int ly, int lz, Pix64& p) {
+  double o[3];
+  pix_offsets<ND>(P, lx, ly, lz, o);
+  p.ox = o[0];
+  p.oy = o[1];
+  p.oz = o[2];
+  p.pad = 0.0;
+}
+
+// Centre of base tile (bx, by, bz), sample units.
+template <int ND>
+__device__ __forceinline__ void tile_ref(const OpParams& P, int bx, int by, int bz, double r[3]) {
+  r[0] = P.org[0] + ((double)bx * Tile<ND>::X + 0.5 * (Tile<ND>::X - 1)) * P.hs;
+  r[1] = P.org[1] + ((double)by * Tile<ND>::Y + 0.5 * (Tile<ND>::Y - 1)) * P.hs;
+  r[2] = ND == 3 ? P.org[2] + ((double)bz * Tile<ND>::Z + 0.5 * (Tile<ND>::Z - 1)) * P.hs : 0.0;
+}
+
+template <int ND>
+__device__ __forceinline__ void sensor_pos(const OpParams& P, int s, double sp[3]) {
+  sp[0] = P.sensors[(size_t)s * ND + 0] * P.inv_cdt;
+  sp[1] = P.sensors[(size_t)s * ND + 1] * P.inv_cdt;
+  sp[2] = ND == 3 ? P.sensors[(size_t)s * ND + 2] * P.inv_cdt : 0.0;
+}
+
+// First sample of the LDS window that covers every tap of every pixel centre
+// in the box [lo, hi] (sample units) for a sensor at sp.
+template <int ND>
+__device__ __forceinline__ int window_lo(const OpParams& P, const double lo[3], const double hi[3],
+                                         const double sp[3], bool* in_trace, int width) {
+  double dmin2 = 0.0, dmax2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    double e = fmax(fmax(lo[a] - sp[a], sp[a] - hi[a]), 0.0);
+    dmin2 += e * e;
+    double f = fmax(fabs(lo[a] - sp[a]), fabs(hi[a] - sp[a]));
+    dmax2 += f * f;
+  }
+  double dmin = fmax(sqrt(dmin2), P.rmin);
+  double dmax = fmax(sqrt(dmax2), P.rmin);
+  double tmin = dmin - (double)P.t0i - P.t0fd;
+  double tmax = dmax - (double)P.t0i - P.t0fd;
+  *in_trace = tmax >= -2.0 && tmin <= (double)P.K + 1.0 && dmax < 4.0e6;
+  double klo = floor(tmin) - 1.0;
+  klo = fmin(fmax(klo, -4.0 * width), (double)P.K + 4.0);  // keep integer conversions in range
+  return (int)klo;
+}
+
+template <int ND>
+__device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], const double sp[3], int klo,
+                                        int row_elems, int esz, bool active, SC32& c) {
+  double dx = ref[0] - sp[0], dy = ref[1] - sp[1], dz = ND == 3 ? ref[2] - sp[2] : 0.0;
+  double ra2 = dx * dx + dy * dy + dz * dz;
+  double kr = rint(sqrt(ra2));
+  if (!active) {  // benign constants: bounded delay, zero weight
+    c.E = 0.f; c.DX2 = 0.f; c.DY2 = 0.f; c.DZ2 = 0.f; c.KRN = 0.f; c.KR2N = 0.f; c.KR2 = 0.f;
+    c.CMIN = kInactiveCmin; c.BASE = row_elems * esz; c.act = 0; c.HALF = 0.f;
+    return;
+  }
+  c.E = (float)(ra2 - kr * kr);
+  c.DX2 = (float)(2.0 * dx);
+  c.DY2 = (float)(2.0 * dy);
+  c.DZ2 = (float)(2.0 * dz);
+  c.KRN = (float)(-kr);
+  c.KR2N = (float)(-2.0 * kr);
+  c.KR2 = (float)(kr * kr);
+  c.CMIN = (float)(P.rmin * P.rmin - kr * kr);
+  c.BASE = ((int)kr - P.t0i - klo + row_elems) * esz;
+  c.act = 1;
+  c.HALF = 0.5f;
+}
+
+template <int ND>
+__device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], const double sp[3], int klo,
+                                        int row_elems, int esz, bool active, SC64& c) {
+  double dx = ref[0] - sp[0], dy = ref[1] - sp[1], dz = ND == 3 ? ref[2] - sp[2] : 0.0;
+  double kr = active ? rint(sqrt(dx * dx + dy * dy + dz * dz)) : 0.0;
+  c.DX = active ? dx : 0.0;
+  c.DY = active ? dy : 0.0;
+  c.DZ = active ? dz : 0.0;
+  c.KR = kr;
+  c.RMIN2 = active ? P.rmin * P.rmin : 1.0;
+  c.ACT = active ? 1.0 : 0.0;
+  c.T0F = P.t0fd;
+  c.BASE = ((int)kr - P.t0i - klo + row_elems) * esz;
+  c.act = active ? 1 : 0;
+}
+
+// FP64 sensor vector and reference of a "near" (tile, sensor) pair, used by
+// the FP32 kernels: when a sensor lies within a few tile half-diagonals of
+// the tile, R can be small against the tile-local terms of num, so the delay
+// and weight of such pairs are formed from FP64 coordinates instead.
+struct Near32 {
+  double DX, DY, DZ, KR;
+};
+static_assert(sizeof(Near32) == 32, "Near32 layout");
+
+// The per-pair arithmetic.  Returns the LDS byte address of tap k0 (rows of
+// ESZ-byte elements), the fraction f and the tap weight in kernel units
+// (FP32: 1 / (2R); FP64: 1 / R).
+template <int ND, bool FRAC, int ESZ>
+__device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, int& kbyte, float& f, float& wt) {
+  float t = px.q + c.E;
+  float num = fmaf(px.oy, c.DY2, t);
+  if (ND == 3) num = fmaf(px.oz, c.DZ2, num);
+  num = fmaf(px.ox, c.DX2, num);
+  num = fmaxf(num, c.CMIN);
+  const float R2 = num + c.KR2;
+  const float w = __builtin_amdgcn_rsqf(R2);
+  const float da = fmaf(R2, w, c.KRN);       // R - kr, FP32 estimate
+  const float r1 = fmaf(c.KR2N, da, num);
+  const float r = fmaf(-da, da, r1);         // num - da (da + 2 kr)
+  wt = c.HALF * w;                           // 1 / (2R)
+  float d = fmaf(r, wt, da);                 // Newton-corrected R - kr
+  if (FRAC) d = d - t0f;
+  f = __builtin_amdgcn_fractf(d);           // d - floor(d), exact
+  kbyte = (int)floorf(d) * ESZ + c.BASE;
+}
+
+// FP32 kernels, near pairs: delay and weight from FP64 coordinates.
+template <int ND, bool FRAC, int ESZ>
+__device__ __forceinline__ void phase_near(const Near32& n, const double o[3], double rmin2, double t0fd, int base,
+                                           float half, int& kbyte, float& f, float& wt) {
+  const double dx = o[0] + n.DX;
+  const double dy = o[1] + n.DY;
+  double R2 = dx * dx + dy * dy;
+  if (ND == 3) {
+    const double dz = o[2] + n.DZ;
+    R2 = R2 + dz * dz;
+  }
+  R2 = fmax(R2, rmin2);
+  const double R = sqrt(R2);
+  double d = R - n.KR;
+  if (FRAC) d = d - t0fd;
+  const double fl = floor(d);
+  f = (float)(d - fl);
+  wt = (float)((double)half / R);
+  kbyte = (int)fl * ESZ + base;
+}
+
+template <int ND, bool FRAC, int ESZ>
+__device__ __forceinline__ void phase(const SC64& c, const Pix64& px, float, int& kbyte, double& f, double& wt) {
+  const double dx = px.ox + c.DX;
+  const double dy = px.oy + c.DY;
+  double R2 = dx * dx + dy * dy;
+  if (ND == 3) {
+    const double dz = px.oz + c.DZ;
+    R2 = R2 + dz * dz;
+  }
+  R2 = fmax(R2, c.RMIN2);
+  const double R = sqrt(R2);
+  wt = c.ACT / R;
+  double d = R - c.KR;
+  if (FRAC) d = d - c.T0F;
+  const double fl = floor(d);
+  f = d - fl;
+  kbyte = (int)fl * ESZ + c.BASE;
+}
+
+// Atomic add through an LDS byte address held in an integer register.
+template <typename T>
+__device__ __forceinline__ void lds_add(T* addr, T v) {
+  __hip_atomic_fetch_add(reinterpret_cast<__attribute__((address_space(3))) T*>(static_cast<unsigned>(reinterpret_cast<size_t>(addr))),
+                         v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Load through an LDS byte address held in an integer register.
+template <typename T>
+__device__ __forceinline__ T lds_load(const T* addr) {
+  return *reinterpret_cast<const __attribute__((address_space(3))) T*>(
+      static_cast<unsigned>(reinterpret_cast<size_t>(addr)));
+}
+
+template <typename T> constexpr size_t near_bytes() { return sizeof(T) == 4 ? sizeof(Near32) : 0; }
+
+__device__ __forceinline__ bool is_near(const OpParams& P, const double ref[3], const double sp[3]) {
+  const double dx = ref[0] - sp[0], dy = ref[1] - sp[1], dz = ref[2] - sp[2];
+  return dx * dx + dy * dy + dz * dz < P.near_r2;
+}
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// A^T: one work-group per base tile, one pixel per lane.  Sensors are taken in
+// chunks: the chunk's per-sensor constants and each sensor's trace window
+// (the samples any pixel of the tile can reach, zero outside 0..K-1) are
+// staged in LDS, then every lane gathers its two taps per sensor from LDS.
+// Within a chunk the sensors are ordered far-first (a deterministic
+// compaction), so the fast FP32 loop runs without per-sensor tests and the
+// few near sensors follow in an FP64-delay loop.
+// With CG the epilogue also performs x += alpha p, s = A^T r - lambda x and the
+// FP64 partial sums of ||s||^2 and ||x||^2.
+template <typename T, int ND, bool FRAC, bool CG>
+__device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, const T* __restrict__ y,
+                                        T* __restrict__ out, T* __restrict__ xcg, const T* __restrict__ pcg,
+                                        const double* __restrict__ alpha, double lambda,
+                                        double* __restrict__ part_s, double* __restrict__ part_x) {
+  using SC = typename SCOf<T>::type;
+  using PX = typename PixOf<T>::type;
+  constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
+  constexpr bool F32 = sizeof(T) == 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BpLayout L = bp_layout(P.sc, P.wp, sizeof(T), sizeof(SC), near_bytes<T>());
+  SC* sct = reinterpret_cast<SC*>(smem + L.sct);
+  int* klo_s = reinterpret_cast<int*>(smem + L.klo);
+  int* sid = reinterpret_cast<int*>(smem + L.sid);
+  Near32* ntab = reinterpret_cast<Near32*>(smem + L.nd);
+  T* win = reinterpret_cast<T*>(smem + L.win);
+  __shared__ double red[4];
+  __shared__ int cnt[8];
+
+  const int bx = tile % P.ntile[0];
+  const int by = (tile / P.ntile[0]) % P.ntile[1];
+  const int bz = tile / (P.ntile[0] * P.ntile[1]);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+  const int ix = bx * TX + lx, iy = by * TY + ly, iz = bz * TZ + lz;
+  const bool valid = ix < P.nx && iy < P.ny && iz < P.nz;
+
+  double ref[3], lo[3], hi[3];
+  tile_ref<ND>(P, bx, by, bz, ref);
+  {
+    const int T3[3] = {TX, TY, TZ};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double half = 0.5 * (T3[a] - 1) * P.hs;
+      lo[a] = ref[a] - half;
+      hi[a] = ref[a] + half;
+    }
+  }
+  PX px;
+  make_pix<ND>(P, lx, ly, lz, px);
+  const float t0f = P.t0f;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+
+  T acc = 0;
+  for (int s0 = 0; s0 < P.S; s0 += P.sc) {
+    const int nsc = min(P.sc, P.S - s0);
+    const bool mine = tid < nsc;
+    double sp[3] = {0.0, 0.0, 0.0};
+    bool in_trace = false, near = false;
+    int kl = 0;
+    if (mine) {
+      sensor_pos<ND>(P, s0 + tid, sp);
+      kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wp);
+      near = F32 && in_trace && is_near(P, ref, sp);
+    }
+    // far sensors first, then near ones; order within each group = sensor order
+    const unsigned long long bfar = __ballot(mine && !near);
+    const unsigned long long bnear = __ballot(mine && near);
+    if (lane == 0) {
+      cnt[wave] = __popcll(bfar);
+      cnt[4 + wave] = __popcll(bnear);
+    }
+    __syncthreads();
+    const int nfar = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    int far_before = 0, near_before = 0;
+    for (int w = 0; w < wave; ++w) {
+      far_before += cnt[w];
+      near_before += cnt[4 + w];
+    }
+    if (mine) {
+      const int pos = near ? nfar + near_before + __popcll(bnear & lt_mask) : far_before + __popcll(bfar & lt_mask);
+      SC c;
+      make_sc<ND>(P, ref, sp, kl, pos * P.wp, (int)sizeof(T), in_trace, c);
+      c.BASE += (int)(size_t)win;  // absolute LDS byte address of the row's reference sample
+      sct[pos] = c;
+      klo_s[pos] = in_trace ? kl : P.K + 8;  // inactive rows stage zeros
+      sid[pos] = s0 + tid;
+      if (near) {
+        Near32 n;
+        n.DX = ref[0] - sp[0];
+        n.DY = ref[1] - sp[1];
+        n.DZ = ref[2] - sp[2];
+        n.KR = rint(sqrt(n.DX * n.DX + n.DY * n.DY + n.DZ * n.DZ));
+        ntab[pos] = n;
+      }
+    }
+    __syncthreads();
+    const int tot = nsc * P.wp;
+    for (int e = tid; e < tot; e += kBlock) {
+      const int j = (int)__umulhi((unsigned)e, P.wp_magic);
+      const int k = klo_s[j] + (e - j * P.wp);
+      T v = 0;
+      if (k >= 0 && k < P.K) v = y[(size_t)sid[j] * P.K + k];
+      win[e] = v;
+    }
+    __syncthreads();
+    // Sensors whose arrivals miss the trace carry zero weight and a bounded
+    // delay into a zero row, so the loop needs no per-sensor test.
+    // Four sensors per step: four delays, then four independent window
+    // reads, then the sums in sensor order (the order never changes).
+    int j = 0;
+    for (; j + 4 <= nfar; j += 4) {
+      int kb[4];
+      T f[4], wt[4], y0[4], y1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) phase<ND, FRAC, (int)sizeof(T)>(sct[j + u], px, t0f, kb[u], f[u], wt[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb[u]));
+        y0[u] = lds_load(tap);
+        y1[u] = lds_load(tap + 1);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = fma(wt[u], fma(f[u], y1[u] - y0[u], y0[u]), acc);
+    }
+    for (; j < nfar; ++j) {
+      int kb;
+      T f, wt;
+      phase<ND, FRAC, (int)sizeof(T)>(sct[j], px, t0f, kb, f, wt);
+      const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
+      const T y0 = lds_load(tap);
+      const T y1 = lds_load(tap + 1);
+      acc = fma(wt, fma(f, y1 - y0, y0), acc);
+    }
+    if constexpr (F32) {
+      if (nfar < nsc) {
+        double o[3];
+        pix_offsets<ND>(P, lx, ly, lz, o);
+        for (; j < nsc; ++j) {
+          const SC32& c = sct[j];
+          int kb;
+          float f, wt;
+          phase_near<ND, FRAC, 4>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, c.HALF, kb, f, wt);
+          const float* tap = reinterpret_cast<const float*>(static_cast<size_t>(kb));
+          const float y0 = lds_load(tap);
+          const float y1 = lds_load(tap + 1);
+          acc = fmaf(wt, fmaf(f, y1 - y0, y0), acc);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const size_t idx = ((size_t)iz * P.ny + iy) * P.nx + ix;
+  const T scale = F32 ? (T)P.out_scale : (T)P.out_scale_d;
+  if (!CG) {
+    if (valid) out[idx] = acc * scale;
+    return;
+  }
+  double ss = 0.0, xx = 0.0;
+  if (valid) {
+    const double a = *alpha;
+    double xo = (double)xcg[idx];
+    if (a != 0.0) xo += a * (double)pcg[idx];
+    const T xn = (T)xo;
+    const T sn = (T)((double)(acc * scale) - lambda * (double)xn);
+    out[idx] = sn;
+    xcg[idx] = xn;
+    ss = (double)sn * (double)sn;
+    xx = (double)xn * (double)xn;
+  }
+  ss = block_sum(ss, red);
+  xx = block_sum(xx, red);
+  if (tid == 0) {
+    part_s[pidx] = ss;
+    part_x[pidx] = xx;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A, pass 1: one work-group per (forward tile, chunk of 64 sensors); lane =
+// sensor, wave w walks base tiles w, w+4, ... of the forward tile one pixel at
+// a time (the pixel is uniform across the wave).  Each lane scatters its two
+// taps into its own sensor's LDS histogram row, so the lanes of one ds_add
+// never collide on an address.  The rows are then written out with plain
+// coalesced stores, with the first sample of each row in a table.
+template <typename T, int ND, bool FRAC>
+__device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __restrict__ x, T* __restrict__ rows,
+                                        int* __restrict__ klo_tab) {
+  using SC = typename SCOf<T>::type;
+  using PX = typename PixOf<T>::type;
+  constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
+  constexpr int NS = kSensorsPerFwdBlock;
+  constexpr bool F32 = sizeof(T) == 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const FpLayout L = fp_layout(P.wpa, P.nsub, sizeof(T), sizeof(PX));
+  // The histogram accumulates in FP64 in both precisions: FP64 LDS adds are
+  // fast on gfx950 (and FP32 LDS float adds are not), and they sum exactly
+  // enough that the rows round to FP32 only once, when they are written out.
+  double* hist = reinterpret_cast<double*>(smem + L.hist);
+  PX* pixtab = reinterpret_cast<PX*>(smem + L.pixtab);
+  T* xs = reinterpret_cast<T*>(smem + L.xs);
+  int* klo_a = reinterpret_cast<int*>(smem + L.klo);
+
+  const int chunk = b % P.n_chunks;
+  const int at = b / P.n_chunks;
+  const int ax = at % P.natile[0];
+  const int ay = (at / P.natile[0]) % P.natile[1];
+  const int az = at / (P.natile[0] * P.natile[1]);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+  const int s = chunk * NS + lane;
+  const bool s_ok = s < P.S;
+
+  // pixel offsets of a base tile (same for every base tile) and the forward tile's x values
+  {
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    make_pix<ND>(P, lx, ly, lz, pixtab[tid]);
+    for (int m = 0; m < P.nsub; ++m) {
+      const int bx = ax * P.msub[0] + m % P.msub[0];
+      const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
+      const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
+      const int ix = bx * TX + lx, iy = by * TY + ly, iz = bz * TZ + lz;
+      T v = 0;
+      if (ix < P.nx && iy < P.ny && iz < P.nz) v = x[((size_t)iz * P.ny + iy) * P.nx + ix];
+      xs[m * kBlock + tid] = v;
+    }
+  }
+  // this lane's sensor and its window over the whole forward tile
+  double sp[3];
+  sensor_pos<ND>(P, s_ok ? s : P.S - 1, sp);
+  bool in_trace;
+  int kl;
+  {
+    double lo[3], hi[3];
+    const int T3[3] = {TX, TY, TZ};
+    double r0[3];
+    tile_ref<ND>(P, ax * P.msub[0], ay * P.msub[1], az * P.msub[2], r0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
+      hi[a] = lo[a] + (P.msub[a] * T3[a] - 1) * P.hs;
+    }
+    if (ND == 2) { lo[2] = 0.0; hi[2] = 0.0; }
+    kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wpa);
+  }
+  const bool active = s_ok && in_trace;
+  if (wave == 0) klo_a[lane] = active ? kl : P.K + 8;
+  for (int e = tid; e < NS * P.wpa; e += kBlock) hist[e] = 0;
+  __syncthreads();
+
+  const float t0f = P.t0f;
+  for (int m = wave; m < P.nsub; m += 4) {
+    const int bx = ax * P.msub[0] + m % P.msub[0];
+    const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
+    const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
+    const int nlx = __builtin_amdgcn_readfirstlane(min(TX, P.nx - bx * TX));
+    const int nly = __builtin_amdgcn_readfirstlane(min(TY, P.ny - by * TY));
+    const int nlz = __builtin_amdgcn_readfirstlane(min(TZ, P.nz - bz * TZ));
+    if (nlx <= 0 || nly <= 0 || nlz <= 0) continue;
+    double ref[3];
+    tile_ref<ND>(P, bx, by, bz, ref);
+    SC c;
+    make_sc<ND>(P, ref, sp, kl, lane * P.wpa, 8, active, c);
+    c.BASE += (int)(size_t)hist;  // absolute LDS byte address
+    asm volatile("" : "+v"(c.BASE));  // keep "k * 4 + BASE" a single shift-add
+    const T* xm = xs + m * kBlock;
+    const bool near = F32 && active && is_near(P, ref, sp);
+    if (__ballot(near) == 0) {
+      for (int lz = 0; lz < nlz; ++lz) {
+        for (int ly = 0; ly < nly; ++ly) {
+          const int rowp = (lz * TY + ly) * TX;
+#pragma unroll 2
+          for (int lx = 0; lx < nlx; ++lx) {
+            const PX px = pixtab[rowp + lx];
+            const T xp = xm[rowp + lx];
+            int kb;
+            T f, wt;
+            phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
+            const double v = (double)(wt * xp);
+            const double a1 = v * (double)f;
+            const double a0 = v - a1;
+            double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
+            lds_add(bin, a0);
+            lds_add(bin + 1, a1);
+          }
+        }
+      }
+    } else if constexpr (F32) {
+      // some lane's sensor is near this tile: those lanes take the FP64 delay
+      Near32 nn;
+      nn.DX = ref[0] - sp[0];
+      nn.DY = ref[1] - sp[1];
+      nn.DZ = ref[2] - sp[2];
+      nn.KR = rint(sqrt(nn.DX * nn.DX + nn.DY * nn.DY + nn.DZ * nn.DZ));
+      const double rmin2 = P.rmin * P.rmin;
+      for (int lz = 0; lz < nlz; ++lz) {
+        for (int ly = 0; ly < nly; ++ly) {
+          const int rowp = (lz * TY + ly) * TX;
+          for (int lx = 0; lx < nlx; ++lx) {
+            const Pix32 px = pixtab[rowp + lx];
+            const float xp = xm[rowp + lx];
+            int kb;
+            float f, wt;
+            if (near) {
+              double o[3];
+              pix_offsets<ND>(P, lx, ly, lz, o);
+              phase_near<ND, FRAC, 8>(nn, o, rmin2, P.t0fd, c.BASE, c.HALF, kb, f, wt);
+            } else {
+              phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
+            }
+            const double v = (double)(wt * xp);
+            const double a1 = v * (double)f;
+            const double a0 = v - a1;
+            double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
+            lds_add(bin, a0);
+            lds_add(bin + 1, a1);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // histogram rows out, row (forward tile, sensor) at ((at * S) + s) * wpa
+  for (int j = wave; j < NS; j += 4) {
+    const int sj = chunk * NS + j;
+    if (sj >= P.S) break;
+    T* row = rows + ((size_t)at * P.S + sj) * P.wpa;
+    for (int i = lane; i < P.wpa; i += 64) row[i] = (T)hist[j * P.wpa + i];
+  }
+  if (wave == 0 && s_ok) klo_tab[(size_t)at * P.S + s] = klo_a[lane];
+}
+
+// A, pass 2: one work-group per (sensor, segment of kseg samples).  Wave w
+// adds the rows of forward tiles w, w+4, ... (in increasing order) into its
+// own LDS copy of the segment; the four copies are then summed in a fixed
+// order, scaled and written to y, with the FP64 partial of ||y||^2.  No
+// atomics: the result is the same on every run.
+template <typename T>
+__device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx, const T* __restrict__ rows,
+                                            const int* __restrict__ klo_tab, T* __restrict__ y,
+                                            double* __restrict__ part_q) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* tr = reinterpret_cast<T*>(smem);
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int s = blk / P.nseg;
+  const int seg = blk - s * P.nseg;
+  const int k0 = seg * P.kseg;
+  const int kn = min(P.kseg, P.K - k0);
+  for (int i = tid; i < 4 * P.kseg; i += kBlock) tr[i] = 0;
+  __syncthreads();
+  T* mine = tr + wave * P.kseg;
+  for (int at = wave; at < P.n_atiles; at += 4) {
+    const int kl = __builtin_amdgcn_readfirstlane(klo_tab[(size_t)at * P.S + s]);
+    const int lo = max(kl, k0), hi = min(kl + P.wpa, k0 + kn);
+    if (lo >= hi) continue;
+    const T* row = rows + ((size_t)at * P.S + s) * P.wpa;
+    for (int k = lo + lane; k < hi; k += 64) mine[k - k0] += row[k - kl];
+  }
+  __syncthreads();
+  const T scale = sizeof(T) == 4 ? (T)P.out_scale : (T)P.out_scale_d;
+  double acc = 0.0;
+  T* yrow = y + (size_t)s * P.K + k0;
+  for (int i = tid; i < kn; i += kBlock) {
+    const T v = (((tr[i] + tr[P.kseg + i]) + tr[2 * P.kseg + i]) + tr[3 * P.kseg + i]) * scale;
+    yrow[i] = v;
+    acc += (double)v * (double)v;
+  }
+  if (part_q) {
+    acc = block_sum(acc, red);
+    if (tid == 0) part_q[pidx] = acc;
+  }
+}
+
+}  // namespace
+
+}  // namespace pa

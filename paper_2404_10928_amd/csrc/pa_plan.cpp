@@ -148,7 +148,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     int (*cand)[3] = nd == 2 ? cand2 : cand3;
     const int ncand = nd == 2 ? 2 : 4;
     bool ok = false;
-    for (size_t budget : {kLdsPreferred, kLdsMax}) {
+    for (size_t budget : {kLdsPreferredFwd, kLdsMax}) {
       for (int ci = 0; ci < ncand && !ok; ++ci) {
         int* m = cand[ci];
         double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;

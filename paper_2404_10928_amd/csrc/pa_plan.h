@@ -30,6 +30,7 @@ constexpr int kBlock = 256;          // lanes per work-group, every kernel
 constexpr int kSensorsPerFwdBlock = 64;  // forward operator: one sensor per lane of a wave
 constexpr size_t kLdsPreferred = 64 * 1024 - 256;  // dynamic LDS that keeps several work-groups per CU
 constexpr size_t kLdsMax = 160 * 1024 - 1024;      // gfx950: 160 KiB of LDS per work-group, minus static use
+constexpr size_t kLdsPreferredFwd = 80 * 1024;      // forward pass 1: two work-groups per CU
 
 // Everything a kernel needs about the operator, by value.  Lengths are in
 // "sample units": metres multiplied by 1 / (c dt), so a distance equals its
@@ -84,10 +85,11 @@ PA_HD inline BpLayout bp_layout(int sc, int wp, size_t elem, size_t sc_bytes, si
 struct FpLayout {
   size_t hist, pixtab, xs, klo, total;
 };
+// The forward histogram is FP64 in both precisions (elem is the x element size).
 PA_HD inline FpLayout fp_layout(int wpa, int nsub, size_t elem, size_t pix_bytes) {
   FpLayout L;
   L.hist = 0;
-  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * elem);
+  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * sizeof(double));
   L.xs = L.pixtab + (size_t)kBlock * pix_bytes;
   L.klo = L.xs + align16((size_t)nsub * kBlock * elem);
   L.total = L.klo + kSensorsPerFwdBlock * 4;
@@ -112,6 +114,25 @@ struct Plan {
 // Fills *plan from g.  Returns PA_OK or an error with *msg set.  Never touches
 // the GPU or dereferences g->sensors.
 pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg);
+
+// One frame of a batch as the batched kernels see it (device table, sorted
+// by work per block, largest first).  Block ranges are those of each batched
+// launch; partial sums are stored at the frame's first block + local index,
+// so a frame's sums are formed in the same order as in a single-frame call.
+struct FrameDesc {
+  OpParams op;
+  int64_t xo, yo;      // element offsets of the frame's image / traces in the packed buffers
+  int64_t scr;         // byte offset of the frame's forward partial rows in the scratch area
+  int64_t scr_tab;     // byte offset of the frame's window-start table in the scratch area
+  int32_t b_bp, n_bp;  // adjoint blocks
+  int32_t b_fp, n_fp;  // forward pass-1 blocks
+  int32_t b_ga, n_ga;  // forward gather blocks
+  int32_t b_m, n_m;    // BLAS blocks over the frame's S*K samples
+  int32_t b_p, n_p;    // BLAS blocks over the frame's pixels
+  int32_t frame;       // position in the caller's frame order
+  int32_t pad;
+};
+
 
 // Sizes of the BLAS-1 grids (fixed per vector length so every reduction runs
 // in the same order every time).
