@@ -39,6 +39,28 @@ FLOP_PER_PAIR_2D = 18
 PEAK_FP32_VALU_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 
 
+def measured_traffic(which: str):
+    """HBM bytes per apply from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, or None when the operator kernels changed since it was taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "traffic_512x512.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None, "no counter summary"
+    h = hashlib.sha256()
+    for fn in ("pa_ops_dev.h", "pa_ops.hip"):
+        with open(os.path.join(HERE, "paper_2404_10928_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("kernel_sources_sha256"):
+        return None, "kernels changed since the counters were taken"
+    k = rec["per_launch_averages"]
+    if which == "forward":
+        return rec["forward_operator_hbm_bytes"], "FETCH_SIZE + WRITE_SIZE of both launches, copy-calibrated"
+    return k["bp_kernel_cg"]["hbm_bytes"], "FETCH_SIZE + WRITE_SIZE, copy-calibrated (CG-epilogue instance)"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,16 +167,24 @@ def main():
             "us_per_apply": {"A": t_fwd * 1e6, "AT": t_adj * 1e6, "A+AT": t_pair * 1e6},
             "pairs_per_s": {"A": pairs / t_fwd, "AT": pairs / t_adj},
         })
-        # The dominant kernel of a CGLS iteration: the slower of the two operators.
-        # The forward call includes a small zero-fill of y (1 launch, 2 MiB); the
-        # adjoint call is a single kernel.
-        dom, t_dom = ("A (fp_kernel, scatter)", t_fwd) if t_fwd > t_adj else ("A^T (bp_kernel, gather)", t_adj)
+        # The dominant kernel of a CGLS iteration: the slower of the two
+        # operators.  The forward operator is two launches per apply (the
+        # per-sensor histogram scatter and the gather of its partial rows);
+        # the adjoint is one.
+        if t_fwd > t_adj:
+            dom, t_dom, tkey = "A (fp_kernel + fp_gather_kernel, two launches per apply)", t_fwd, "forward"
+        else:
+            dom, t_dom, tkey = "A^T (bp_kernel)", t_adj, "adjoint"
         achieved = pairs * FLOP_PER_PAIR_2D / t_dom / 1e12
+        traffic, traffic_note = measured_traffic(tkey)
         out["roofline"] = {
             "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
             "work_per_launch": f"{pairs} pixel-sensor pairs x {FLOP_PER_PAIR_2D} FLOP",
+            "traffic_note": traffic_note,
         }
+        if traffic:
+            out["roofline"]["hbm_GBps_at_measured_traffic"] = traffic / t_dom / 1e9
         print(f"[bench] A {t_fwd*1e6:.1f} us, A^T {t_adj*1e6:.1f} us, A+A^T {t_pair*1e6:.1f} us",
               file=sys.stderr, flush=True)
 

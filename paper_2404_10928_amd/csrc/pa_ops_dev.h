@@ -540,56 +540,60 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
     if (nlx <= 0 || nly <= 0 || nlz <= 0) continue;
     double ref[3];
     tile_ref<ND>(P, bx, by, bz, ref);
-    SC c;
-    make_sc<ND>(P, ref, sp, kl, lane * P.wpa, 8, active, c);
-    c.BASE += (int)(size_t)hist;  // absolute LDS byte address
-    asm volatile("" : "+v"(c.BASE));  // keep "k * 4 + BASE" a single shift-add
-    const T* xm = xs + m * kBlock;
+    // Near (tile, sensor) pairs take benign zero-weight constants here and
+    // are added afterwards, one sensor at a time with one pixel per lane, so
+    // the wave never runs the FP64 delay path for all of its pixels.
     const bool near = F32 && active && is_near(P, ref, sp);
-    if (__ballot(near) == 0) {
-      for (int lz = 0; lz < nlz; ++lz) {
-        for (int ly = 0; ly < nly; ++ly) {
-          const int rowp = (lz * TY + ly) * TX;
+    SC c;
+    make_sc<ND>(P, ref, sp, kl, lane * P.wpa, 8, active && !near, c);
+    c.BASE += (int)(size_t)hist;  // absolute LDS byte address
+    asm volatile("" : "+v"(c.BASE));  // keep "k * 8 + BASE" a single shift-add
+    const T* xm = xs + m * kBlock;
+    for (int lz = 0; lz < nlz; ++lz) {
+      for (int ly = 0; ly < nly; ++ly) {
+        const int rowp = (lz * TY + ly) * TX;
 #pragma unroll 2
-          for (int lx = 0; lx < nlx; ++lx) {
-            const PX px = pixtab[rowp + lx];
-            const T xp = xm[rowp + lx];
-            int kb;
-            T f, wt;
-            phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
-            const double v = (double)(wt * xp);
-            const double a1 = v * (double)f;
-            const double a0 = v - a1;
-            double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
-            lds_add(bin, a0);
-            lds_add(bin + 1, a1);
-          }
+        for (int lx = 0; lx < nlx; ++lx) {
+          const PX px = pixtab[rowp + lx];
+          const T xp = xm[rowp + lx];
+          int kb;
+          T f, wt;
+          phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
+          const double v = (double)(wt * xp);
+          const double a1 = v * (double)f;
+          const double a0 = v - a1;
+          double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
+          lds_add(bin, a0);
+          lds_add(bin + 1, a1);
         }
       }
-    } else if constexpr (F32) {
-      // some lane's sensor is near this tile: those lanes take the FP64 delay
-      Near32 nn;
-      nn.DX = ref[0] - sp[0];
-      nn.DY = ref[1] - sp[1];
-      nn.DZ = ref[2] - sp[2];
-      nn.KR = rint(sqrt(nn.DX * nn.DX + nn.DY * nn.DY + nn.DZ * nn.DZ));
-      const double rmin2 = P.rmin * P.rmin;
-      for (int lz = 0; lz < nlz; ++lz) {
-        for (int ly = 0; ly < nly; ++ly) {
-          const int rowp = (lz * TY + ly) * TX;
-          for (int lx = 0; lx < nlx; ++lx) {
-            const Pix32 px = pixtab[rowp + lx];
-            const float xp = xm[rowp + lx];
+    }
+    if constexpr (F32) {
+      uint64_t nm = __ballot(near);
+      if (nm != 0) {
+        const double rmin2 = P.rmin * P.rmin;
+        // this lane's row base for its own sensor, as the far constants would have it
+        const double kr_l = rint(sqrt((ref[0] - sp[0]) * (ref[0] - sp[0]) + (ref[1] - sp[1]) * (ref[1] - sp[1]) +
+                                      (ref[2] - sp[2]) * (ref[2] - sp[2])));
+        const int base_l = ((int)kr_l - P.t0i - kl + lane * P.wpa) * 8 + (int)(size_t)hist;
+        while (nm != 0) {
+          const int j = __builtin_ctzll(nm);
+          nm &= nm - 1;
+          Near32 nn;
+          nn.DX = ref[0] - __shfl(sp[0], j);
+          nn.DY = ref[1] - __shfl(sp[1], j);
+          nn.DZ = ref[2] - __shfl(sp[2], j);
+          nn.KR = __shfl(kr_l, j);
+          const int base = __shfl(base_l, j);
+          for (int pix = lane; pix < TX * TY * TZ; pix += 64) {
+            const int lx = pix % TX, ly = (pix / TX) % TY, lz = pix / (TX * TY);
+            if (lx >= nlx || ly >= nly || lz >= nlz) continue;
+            double o[3];
+            pix_offsets<ND>(P, lx, ly, lz, o);
             int kb;
             float f, wt;
-            if (near) {
-              double o[3];
-              pix_offsets<ND>(P, lx, ly, lz, o);
-              phase_near<ND, FRAC, 8>(nn, o, rmin2, P.t0fd, c.BASE, c.HALF, kb, f, wt);
-            } else {
-              phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
-            }
-            const double v = (double)(wt * xp);
+            phase_near<ND, FRAC, 8>(nn, o, rmin2, P.t0fd, base, 0.5f, kb, f, wt);
+            const double v = (double)(wt * xm[pix]);
             const double a1 = v * (double)f;
             const double a0 = v - a1;
             double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));

@@ -100,11 +100,21 @@ def test_late_arrivals_dropped(pa):
 
 
 def test_coarse_and_fine_pitch(pa):
-    # many samples per pixel (wide LDS windows) and a fraction of a sample per pixel
-    g = ring_geom(n=(30, 30), S=40, K=900)
-    check_pair(pa, g.replace(dt=g.dt / 3.0, n_samples=2700), 8, dtypes=(np.float32,), label="fine dt")
+    # many samples per pixel (h / (c dt) ~ 13, near the largest pitch the
+    # forward histogram window supports) and a fraction of a sample per pixel
+    g = ring_geom(n=(30, 30), S=40, K=600)
+    assert 12.0 < g.h / (g.c * g.dt) < 14.0
+    check_pair(pa, g, 8, label="fine dt")
     g2 = ring_geom(n=(96, 80), S=32, K=64)
     check_pair(pa, g2, 9, label="coarse dt")
+
+
+def test_pitch_beyond_lds_window_is_unsupported(pa):
+    import paper_2404_10928_amd._lib as L
+    g = ring_geom(n=(30, 30), S=40, K=2700)   # h / (c dt) ~ 60 samples per pixel
+    with pytest.raises(L.PaError) as e:
+        pa.forward(torch.ones(g.image_shape, dtype=torch.float32, device="cuda"), g)
+    assert e.value.status == L.PA_ERR_UNSUPPORTED
 
 
 def test_point_sources_golden(pa):
