@@ -121,6 +121,61 @@ pa_status pa_cgls_solve(const pa_geometry* g, pa_dtype dtype, const void* y, voi
  * device-to-host copy. */
 pa_status pa_cgls_stop_iteration(const void* workspace, int32_t* stop_iter);
 
+/* ------------------------------------------------------------------ batches
+ * Many frames of uneven image size, sensor count and trace length, each with
+ * its own geometry, processed by one launch per step.  Frame i's image and
+ * traces sit in packed buffers at the element offsets pa_batch_offsets()
+ * gives (the frames one after another, in the order passed to
+ * pa_batch_create).  The batched kernels run the single-frame device code on
+ * each frame's own plan and form every partial sum in the same order, so the
+ * adjoint and the solver steps give each frame its single-frame result bit
+ * for bit.  The forward operator's FP64 histogram adds run in hardware order
+ * (in single-frame calls as well), so forward results agree to the rounding
+ * of those sums, and solves to that rounding as CG propagates it.
+ */
+typedef struct pa_batch pa_batch;
+
+/* Plans a batch (host only: no GPU call, no device pointer dereferenced).
+ * frames[i].sensors stay device pointers owned by the caller and must stay
+ * valid while the batch is used.  All frames must share ndim.  *out receives
+ * a handle to free with pa_batch_destroy. */
+pa_status pa_batch_create(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, pa_batch** out);
+
+/* Frees the handle (and the page-locked host copy of its frame table).  The
+ * caller must have synchronised every stream that used it.  NULL is a no-op. */
+pa_status pa_batch_destroy(pa_batch* b);
+
+/* x_offsets[i], y_offsets[i] (i = 0..n_frames, either may be NULL): element
+ * offset of frame i's image and traces in the packed x and y; entry n_frames
+ * is the total. */
+pa_status pa_batch_offsets(const pa_batch* b, int64_t* x_offsets, int64_t* y_offsets);
+
+/* Device workspace (bytes, 256-byte aligned, caller-owned) for
+ * pa_batch_forward / pa_batch_adjoint, and for pa_batch_cgls_solve with
+ * `iters` iterations.  0 means invalid arguments. */
+size_t pa_batch_workspace_bytes(const pa_batch* b);
+size_t pa_batch_cgls_workspace_bytes(const pa_batch* b, int32_t iters);
+
+/* y := A x and x := A^T y frame by frame (the operators of pa_forward and
+ * pa_adjoint).  x, y: packed device buffers of the batch's dtype.  Each call
+ * first copies the frame table into the workspace on the stream. */
+pa_status pa_batch_forward(pa_batch* b, const void* x, void* y, void* workspace, size_t workspace_bytes,
+                           void* hip_stream);
+pa_status pa_batch_adjoint(pa_batch* b, const void* y, void* x, void* workspace, size_t workspace_bytes,
+                           void* hip_stream);
+
+/* pa_cgls_solve on every frame at once, with one lambda and iteration count
+ * and per-frame step sizes and stopping.  history: device double
+ * [n_frames][iters + 1][3] in caller frame order, or NULL.  With PA_USE_GRAPH
+ * the solve's launches are captured once per argument set and replayed. */
+pa_status pa_batch_cgls_solve(pa_batch* b, const void* y, void* x, int32_t iters, double lambda, uint32_t flags,
+                              void* workspace, size_t workspace_bytes, double* history, void* hip_stream);
+
+/* After synchronising: stop[i] = iteration at which frame i stopped early, or
+ * -1.  Returns PA_ERR_BREAKDOWN when any frame stopped early.  One blocking
+ * device-to-host copy. */
+pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int32_t iters, int32_t* stop);
+
 /* Message for the last failing call on this thread ("" if none).  Valid until
  * the next pa_* call on the same thread. */
 const char* pa_last_error(void);

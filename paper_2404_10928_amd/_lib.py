@@ -29,7 +29,9 @@ PA_X0_ZERO = 1
 PA_USE_GRAPH = 2
 
 EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspace_bytes", "pa_cgls_solve",
-           "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version"]
+           "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version", "pa_batch_create", "pa_batch_destroy",
+           "pa_batch_offsets", "pa_batch_workspace_bytes", "pa_batch_cgls_workspace_bytes", "pa_batch_forward",
+           "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations"]
 
 
 class PaGeometry(ctypes.Structure):
@@ -73,6 +75,26 @@ def load(path: str = LIB_PATH):
     lib.pa_last_error.restype = ctypes.c_char_p
     lib.pa_abi_version.argtypes = []
     lib.pa_abi_version.restype = ctypes.c_int32
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.pa_batch_create.argtypes = [gp, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.pa_batch_create.restype = ctypes.c_int
+    lib.pa_batch_destroy.argtypes = [vp]
+    lib.pa_batch_destroy.restype = ctypes.c_int
+    lib.pa_batch_offsets.argtypes = [vp, i64p, i64p]
+    lib.pa_batch_offsets.restype = ctypes.c_int
+    lib.pa_batch_workspace_bytes.argtypes = [vp]
+    lib.pa_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_batch_cgls_workspace_bytes.argtypes = [vp, ctypes.c_int32]
+    lib.pa_batch_cgls_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_batch_forward.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pa_batch_forward.restype = ctypes.c_int
+    lib.pa_batch_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pa_batch_adjoint.restype = ctypes.c_int
+    lib.pa_batch_cgls_solve.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32, vp,
+                                        ctypes.c_size_t, vp, vp]
+    lib.pa_batch_cgls_solve.restype = ctypes.c_int
+    lib.pa_batch_stop_iterations.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.pa_batch_stop_iterations.restype = ctypes.c_int
     _lib = lib
     return lib
 

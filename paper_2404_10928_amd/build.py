@@ -17,11 +17,11 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpa_mi355x.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["pa_plan.cpp", "pa_ops.hip", "pa_blas.hip", "pa_api.hip"]
+SOURCES = ["pa_plan.cpp", "pa_ops.hip", "pa_batch.hip", "pa_blas.hip", "pa_api.hip"]
 # The operator kernels never test for NaN; running them with the IEEE mode bit
 # off lets min/max skip the NaN-quieting of LDS-loaded operands.  The solver
 # kernels keep IEEE mode because they detect non-finite step sizes.
-EXTRA = {"pa_ops.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"]}
+EXTRA = {"pa_ops.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"], "pa_batch.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

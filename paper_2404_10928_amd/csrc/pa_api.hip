@@ -4,12 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <list>
 #include <mutex>
 #include <string>
+#include <vector>
+#include <new>
 
 #include "pa.h"
 #include "pa_kernels.h"
@@ -131,6 +134,7 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
 // ------------------------------------------------------------ graph cache
 
 struct GraphKey {
+  uint64_t batch;   // 0 for single-frame solves, else the batch's id
   pa_geometry g;
   pa_dtype dt;
   const void* y;
@@ -154,7 +158,8 @@ std::list<GraphEntry>* g_graphs = nullptr;  // never destroyed: graphs live unti
 constexpr size_t kMaxGraphs = 16;
 hipStream_t g_capture_stream[64] = {};
 
-hipError_t get_graph(const GraphKey& key, const Solve& S, hipGraphExec_t* out) {
+template <typename Enqueue>
+hipError_t get_graph(const GraphKey& key, Enqueue&& enqueue, hipGraphExec_t* out) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   if (!g_graphs) g_graphs = new std::list<GraphEntry>();
   for (auto it = g_graphs->begin(); it != g_graphs->end(); ++it) {
@@ -169,7 +174,7 @@ hipError_t get_graph(const GraphKey& key, const Solve& S, hipGraphExec_t* out) {
   hipStream_t& cs = g_capture_stream[key.device];
   if (!cs && (e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-  hipError_t ee = enqueue_cgls(S, cs);
+  hipError_t ee = enqueue(cs);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs, &graph);
   if (ee != hipSuccess) {
@@ -230,6 +235,140 @@ hipError_t get_scratch(size_t bytes, hipStream_t st, void** out) {
   if ((e = hipMalloc(&p, bytes)) != hipSuccess) return e;
   g_scr->push_back(ScratchEntry{dev, st, p, bytes});
   *out = p;
+  return hipSuccess;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batches
+
+struct pa_batch {
+  pa::BatchPlan plan;
+  pa::FrameDesc* pinned = nullptr;   // page-locked copy of plan.table (allocated on first use)
+  uint64_t id = 0;
+  std::mutex mu;
+};
+
+namespace {
+
+std::atomic<uint64_t> g_batch_ids{1};
+
+pa::BatchLaunch batch_launch(const pa::BatchPlan& B, unsigned char* ws, const pa::BatchLayout& L) {
+  pa::BatchLaunch bl{};
+  bl.table = reinterpret_cast<const pa::FrameDesc*>(ws + L.table);
+  bl.nf = B.nf;
+  bl.dtype = B.dtype;
+  bl.ndim = B.ndim;
+  bl.frac = B.frac;
+  bl.scratch = ws + L.fwd;
+  bl.bp_grid = B.bp_grid;
+  bl.fp_grid = B.fp_grid;
+  bl.gather_grid = B.gather_grid;
+  bl.m_grid = B.m_grid;
+  bl.p_grid = B.p_grid;
+  bl.bp_lds = B.bp_lds;
+  bl.fp_lds = B.fp_lds;
+  bl.gather_lds = B.gather_lds;
+  bl.P_total = B.P_total;
+  bl.M_total = B.M_total;
+  return bl;
+}
+
+// Copies the frame table into the workspace (ordered on the stream before the
+// work that reads it).
+pa_status upload_table(pa_batch* b, unsigned char* ws, const pa::BatchLayout& L, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(b->mu);
+  const size_t bytes = sizeof(pa::FrameDesc) * (size_t)b->plan.nf;
+  if (!b->pinned) {
+    void* h = nullptr;
+    PA_HIP(hipHostMalloc(&h, bytes, hipHostMallocDefault), "hipHostMalloc (frame table)");
+    std::memcpy(h, b->plan.table.data(), bytes);
+    b->pinned = static_cast<pa::FrameDesc*>(h);
+  }
+  PA_HIP(hipMemcpyAsync(ws + L.table, b->pinned, bytes, hipMemcpyHostToDevice, st), "frame table upload");
+  return PA_OK;
+}
+
+pa_status check_batch_ws(const pa_batch* b, const void* ws, size_t bytes, const pa::BatchLayout& L) {
+  if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+  if (!ws) return set_err(PA_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(ws, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (bytes < L.total) return set_err(PA_ERR_WORKSPACE, "workspace smaller than the size pa_batch_*workspace_bytes() gives");
+  return PA_OK;
+}
+
+pa_status check_batch_vecs(const pa_batch* b, const void* x, const void* y, const void* ws, size_t wsb) {
+  const pa::BatchPlan& B = b->plan;
+  pa_status st;
+  if ((st = check_vec(x, B.P_total, B.elem, "x")) != PA_OK) return st;
+  if ((st = check_vec(y, B.M_total, B.elem, "y")) != PA_OK) return st;
+  if (overlap(x, B.P_total * B.elem, y, B.M_total * B.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  if (overlap(ws, wsb, x, B.P_total * B.elem) || overlap(ws, wsb, y, B.M_total * B.elem))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "workspace overlaps x or y");
+  return PA_OK;
+}
+
+struct BatchSolve {
+  const pa::BatchPlan* B;
+  pa::BatchLayout L;
+  const void* y;
+  void* x;
+  int iters;
+  double lambda;
+  uint32_t flags;
+  unsigned char* ws;
+  double* hist;
+};
+
+// The batched CGLS: the single-frame sequence of launches, each covering
+// every frame, with per-frame scalars.
+hipError_t enqueue_batch_cgls(const BatchSolve& S, hipStream_t st) {
+  const pa::BatchPlan& B = *S.B;
+  const pa::BatchLayout& L = S.L;
+  unsigned char* ws = S.ws;
+  const pa::BatchLaunch bl = batch_launch(B, ws, L);
+  int* status = reinterpret_cast<int*>(ws + L.status);
+  double* gamma = reinterpret_cast<double*>(ws + L.gamma);
+  double* alpha = reinterpret_cast<double*>(ws + L.alpha);
+  double* part_q = reinterpret_cast<double*>(ws + L.part_q);
+  double* part_r = reinterpret_cast<double*>(ws + L.part_r);
+  double* part_s = reinterpret_cast<double*>(ws + L.part_s);
+  double* part_x = reinterpret_cast<double*>(ws + L.part_x);
+  double* part_p = reinterpret_cast<double*>(ws + L.part_p);
+  void* r = ws + L.vec_r;
+  void* q = ws + L.vec_q;
+  void* s = ws + L.vec_s;
+  void* p = ws + L.vec_p;
+  const int as = L.astride;
+  const int hs = 3 * (S.iters + 1);
+  hipError_t e;
+  // slots of frames without adjoint or gather work stay zero for the whole solve
+  if ((e = pa::launch_fill(PA_F64, part_s, B.bp_slots, st)) != hipSuccess) return e;
+  if ((e = pa::launch_fill(PA_F64, part_x, B.bp_slots, st)) != hipSuccess) return e;
+  if ((e = pa::launch_fill(PA_F64, part_q, B.ga_slots, st)) != hipSuccess) return e;
+  if (S.flags & PA_X0_ZERO) {
+    if ((e = pa::launch_fill(B.dtype, S.x, B.P_total, st)) != hipSuccess) return e;
+    if ((e = pa::launch_init_r_batched(bl, r, S.y, nullptr, part_r, status, alpha, as, st)) != hipSuccess) return e;
+  } else {
+    if ((e = pa::launch_forward_batched(bl, S.x, q, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_init_r_batched(bl, r, S.y, q, part_r, status, alpha, as, st)) != hipSuccess) return e;
+  }
+  pa::BatchCg cg{S.x, p, alpha, as, 0, S.lambda, part_s, part_x};
+  if ((e = pa::launch_adjoint_batched(bl, r, s, &cg, st)) != hipSuccess) return e;
+  if ((e = pa::launch_dir_batched(bl, p, s, part_s, part_x, part_r, S.lambda, gamma, as, -1, status, S.hist, hs, part_p,
+                                  st)) != hipSuccess)
+    return e;
+  for (int k = 0; k < S.iters; ++k) {
+    if ((e = pa::launch_forward_batched(bl, p, q, part_q, st)) != hipSuccess) return e;
+    if ((e = pa::launch_upd_r_batched(bl, r, q, part_q, part_p, S.lambda, gamma, alpha, as, status, k, part_r, st)) !=
+        hipSuccess)
+      return e;
+    cg.acol = k + 1;
+    if ((e = pa::launch_adjoint_batched(bl, r, s, &cg, st)) != hipSuccess) return e;
+    if ((e = pa::launch_dir_batched(bl, p, s, part_s, part_x, part_r, S.lambda, gamma, as, k, status, S.hist, hs,
+                                    part_p, st)) != hipSuccess)
+      return e;
+  }
   return hipSuccess;
 }
 
@@ -336,7 +475,7 @@ pa_status pa_cgls_solve(const pa_geometry* g, pa_dtype dtype, const void* y, voi
   key.hist = history;
   PA_HIP(hipGetDevice(&key.device), "hipGetDevice");
   hipGraphExec_t exec = nullptr;
-  PA_HIP(get_graph(key, S, &exec), "CGLS graph capture");
+  PA_HIP(get_graph(key, [&](hipStream_t cs) { return enqueue_cgls(S, cs); }, &exec), "CGLS graph capture");
   PA_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
   return PA_OK;
 }
@@ -348,6 +487,161 @@ pa_status pa_cgls_stop_iteration(const void* workspace, int32_t* stop_iter) {
   PA_HIP(hipMemcpy(&v, workspace, sizeof(int), hipMemcpyDeviceToHost), "read CGLS status");
   *stop_iter = v;
   return v >= 0 ? PA_ERR_BREAKDOWN : PA_OK;
+}
+
+pa_status pa_batch_create(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, pa_batch** out) {
+  g_err.clear();
+  if (!out) return set_err(PA_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  pa::BatchPlan B;
+  std::string msg;
+  pa_status st = pa::make_batch_plan(frames, n_frames, dtype, &B, &msg);
+  if (st != PA_OK) return set_err(st, msg);
+  pa_batch* b = new (std::nothrow) pa_batch();
+  if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "out of host memory");
+  b->plan = std::move(B);
+  b->id = g_batch_ids.fetch_add(1);
+  *out = b;
+  return PA_OK;
+}
+
+pa_status pa_batch_destroy(pa_batch* b) {
+  g_err.clear();
+  if (!b) return PA_OK;
+  hipError_t e = hipSuccess;
+  if (b->pinned) e = hipHostFree(b->pinned);
+  delete b;
+  if (e != hipSuccess) return hip_err(e, "hipHostFree (frame table)");
+  return PA_OK;
+}
+
+pa_status pa_batch_offsets(const pa_batch* b, int64_t* x_offsets, int64_t* y_offsets) {
+  g_err.clear();
+  if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+  for (int i = 0; i <= b->plan.nf; ++i) {
+    if (x_offsets) x_offsets[i] = b->plan.xoff[i];
+    if (y_offsets) y_offsets[i] = b->plan.yoff[i];
+  }
+  return PA_OK;
+}
+
+size_t pa_batch_workspace_bytes(const pa_batch* b) {
+  g_err.clear();
+  if (!b) {
+    set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+    return 0;
+  }
+  return pa::batch_layout(b->plan, 0, false).total;
+}
+
+size_t pa_batch_cgls_workspace_bytes(const pa_batch* b, int32_t iters) {
+  g_err.clear();
+  if (!b) {
+    set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+    return 0;
+  }
+  if (iters < 0) {
+    set_err(PA_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+    return 0;
+  }
+  return pa::batch_layout(b->plan, iters, true).total;
+}
+
+pa_status pa_batch_forward(pa_batch* b, const void* x, void* y, void* workspace, size_t workspace_bytes,
+                           void* hip_stream) {
+  g_err.clear();
+  if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+  const pa::BatchLayout L = pa::batch_layout(b->plan, 0, false);
+  pa_status st;
+  if ((st = check_batch_ws(b, workspace, workspace_bytes, L)) != PA_OK) return st;
+  if ((st = check_batch_vecs(b, x, y, workspace, L.total)) != PA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  if ((st = upload_table(b, ws, L, s)) != PA_OK) return st;
+  PA_HIP(pa::launch_forward_batched(batch_launch(b->plan, ws, L), x, y, nullptr, s), "batched forward kernels");
+  return PA_OK;
+}
+
+pa_status pa_batch_adjoint(pa_batch* b, const void* y, void* x, void* workspace, size_t workspace_bytes,
+                           void* hip_stream) {
+  g_err.clear();
+  if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+  const pa::BatchLayout L = pa::batch_layout(b->plan, 0, false);
+  pa_status st;
+  if ((st = check_batch_ws(b, workspace, workspace_bytes, L)) != PA_OK) return st;
+  if ((st = check_batch_vecs(b, x, y, workspace, L.total)) != PA_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  if ((st = upload_table(b, ws, L, s)) != PA_OK) return st;
+  PA_HIP(pa::launch_adjoint_batched(batch_launch(b->plan, ws, L), y, x, nullptr, s), "batched adjoint kernel");
+  return PA_OK;
+}
+
+pa_status pa_batch_cgls_solve(pa_batch* b, const void* y, void* x, int32_t iters, double lambda, uint32_t flags,
+                              void* workspace, size_t workspace_bytes, double* history, void* hip_stream) {
+  g_err.clear();
+  if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+  if (iters < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+  if (iters > (1 << 20)) return set_err(PA_ERR_UNSUPPORTED, "iters above 2^20");
+  if (!std::isfinite(lambda) || lambda < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "lambda must be finite and >= 0");
+  if (flags & ~(PA_X0_ZERO | PA_USE_GRAPH)) return set_err(PA_ERR_INVALID_ARGUMENT, "unknown flag bits");
+  const pa::BatchLayout L = pa::batch_layout(b->plan, iters, true);
+  pa_status st;
+  if ((st = check_batch_ws(b, workspace, workspace_bytes, L)) != PA_OK) return st;
+  if ((st = check_batch_vecs(b, x, y, workspace, L.total)) != PA_OK) return st;
+  const size_t hbytes = sizeof(double) * 3 * (size_t)(iters + 1) * (size_t)b->plan.nf;
+  if (history && !aligned(history, 8)) return set_err(PA_ERR_INVALID_ARGUMENT, "history is not 8-byte aligned");
+  if (history && (overlap(history, hbytes, workspace, L.total) ||
+                  overlap(history, hbytes, x, b->plan.P_total * b->plan.elem) ||
+                  overlap(history, hbytes, y, b->plan.M_total * b->plan.elem)))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "history overlaps another buffer");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  if ((st = upload_table(b, ws, L, s)) != PA_OK) return st;
+  BatchSolve S{&b->plan, L, y, x, iters, lambda, flags, ws, history};
+  bool use_graph = (flags & PA_USE_GRAPH) != 0;
+  if (use_graph && s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    PA_HIP(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) use_graph = false;
+  }
+  if (!use_graph) {
+    PA_HIP(enqueue_batch_cgls(S, s), "batched CGLS enqueue");
+    return PA_OK;
+  }
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.batch = b->id;
+  key.dt = b->plan.dtype;
+  key.y = y;
+  key.x = x;
+  key.iters = iters;
+  key.lambda = lambda;
+  key.flags = flags;
+  key.ws = workspace;
+  key.hist = history;
+  PA_HIP(hipGetDevice(&key.device), "hipGetDevice");
+  hipGraphExec_t exec = nullptr;
+  PA_HIP(get_graph(key, [&](hipStream_t cs) { return enqueue_batch_cgls(S, cs); }, &exec), "batched CGLS graph capture");
+  PA_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
+  return PA_OK;
+}
+
+pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int32_t iters, int32_t* stop) {
+  g_err.clear();
+  if (!b || !workspace || !stop) return set_err(PA_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (iters < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+  const pa::BatchLayout L = pa::batch_layout(b->plan, iters, true);
+  std::vector<int> v((size_t)b->plan.nf, -1);
+  PA_HIP(hipMemcpy(v.data(), static_cast<const unsigned char*>(workspace) + L.status, sizeof(int) * v.size(),
+                   hipMemcpyDeviceToHost),
+         "read batched CGLS status");
+  bool any = false;
+  for (int i = 0; i < b->plan.nf; ++i) {
+    stop[i] = v[i];
+    any = any || v[i] >= 0;
+  }
+  return any ? PA_ERR_BREAKDOWN : PA_OK;
 }
 
 }  // extern "C"

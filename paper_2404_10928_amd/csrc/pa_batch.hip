@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(kBlock) bp_batched(const FrameDesc* __restrict
   const int f = find_frame<&FrameDesc::b_bp>(B, nf, g);
   const FrameDesc& F = B[f];
   const int tile = g - F.b_bp;
-  bp_body<T, ND, FRAC, CG>(F.op, tile, F.b_bp + tile, y + F.yo, out + F.xo, CG ? xcg + F.xo : nullptr,
+  bp_body<T, ND, FRAC, CG>(F.op, tile, F.s_bp + tile, y + F.yo, out + F.xo, CG ? xcg + F.xo : nullptr,
                            CG ? pcg + F.xo : nullptr, CG ? alpha + (size_t)F.frame * astride + acol : nullptr, lambda,
                            part_s, part_x);
 }
@@ -46,10 +46,10 @@ __global__ void __launch_bounds__(kBlock) gather_batched(const FrameDesc* __rest
     const int s = local / F.op.nseg, k0 = (local - s * F.op.nseg) * F.op.kseg;
     const int kn = min(F.op.kseg, F.op.K - k0);
     for (int i = threadIdx.x; i < kn; i += kBlock) y[F.yo + (size_t)s * F.op.K + k0 + i] = (T)0;
-    if (part_q && threadIdx.x == 0) part_q[F.b_ga + local] = 0.0;
+    if (part_q && threadIdx.x == 0) part_q[F.s_ga + local] = 0.0;
     return;
   }
-  gather_body<T>(F.op, local, F.b_ga + local, reinterpret_cast<const T*>(scratch + F.scr),
+  gather_body<T>(F.op, local, F.s_ga + local, reinterpret_cast<const T*>(scratch + F.scr),
                  reinterpret_cast<const int*>(scratch + F.scr_tab), y + F.yo, part_q);
 }
 

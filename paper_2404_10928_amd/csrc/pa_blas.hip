@@ -22,14 +22,18 @@ __global__ void __launch_bounds__(kBlock) fill_kernel(T* __restrict__ p, int64_t
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = (T)0;
 }
 
+// The bodies below run as work-group `bid` of `nblk`; the single-frame
+// kernels pass their own grid, the batched kernels a frame's block range, so
+// a frame's partial sums come out identical either way.
+
 // r = y - q (q may be NULL); partial sums of ||r||^2; resets the solve state.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) init_r_kernel(T* __restrict__ r, const T* __restrict__ y, const T* __restrict__ q,
-                                                        int64_t m, double* __restrict__ part_r, int* __restrict__ status,
-                                                        double* __restrict__ alpha0) {
+__device__ __forceinline__ void init_r_body(int bid, int nblk, T* __restrict__ r, const T* __restrict__ y,
+                                            const T* __restrict__ q, int64_t m, double* __restrict__ part_r,
+                                            int* __restrict__ status, double* __restrict__ alpha0) {
   __shared__ double red[4];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+  for (int64_t i = (int64_t)bid * kBlock + threadIdx.x; i < m; i += (int64_t)nblk * kBlock) {
     const double v = q ? (double)y[i] - (double)q[i] : (double)y[i];
     const T t = (T)v;
     r[i] = t;
@@ -37,8 +41,8 @@ __global__ void __launch_bounds__(kBlock) init_r_kernel(T* __restrict__ r, const
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) {
-    part_r[blockIdx.x] = acc;
-    if (blockIdx.x == 0) {
+    part_r[bid] = acc;
+    if (bid == 0) {
       *status = -1;
       *alpha0 = 0.0;
     }
@@ -48,11 +52,11 @@ __global__ void __launch_bounds__(kBlock) init_r_kernel(T* __restrict__ r, const
 // delta = ||q||^2 + lambda ||p||^2, alpha = gamma_k / delta (0 once stopped),
 // r -= alpha q, partial sums of ||r||^2.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) upd_r_kernel(T* __restrict__ r, const T* __restrict__ q, int64_t m,
-                                                       const double* __restrict__ part_q, int gq,
-                                                       const double* __restrict__ part_p, int gp, double lambda,
-                                                       const double* __restrict__ gamma_k, double* __restrict__ alpha_k,
-                                                       int* __restrict__ status, int k, double* __restrict__ part_r) {
+__device__ __forceinline__ void upd_r_body(int bid, int nblk, T* __restrict__ r, const T* __restrict__ q, int64_t m,
+                                           const double* __restrict__ part_q, int gq, const double* __restrict__ part_p,
+                                           int gp, double lambda, const double* __restrict__ gamma_k,
+                                           double* __restrict__ alpha_k, int* __restrict__ status, int k,
+                                           double* __restrict__ part_r) {
   __shared__ double red[4];
   const double qq = sum_partials(part_q, gq, red);
   const double pp = sum_partials(part_p, gp, red);
@@ -62,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) upd_r_kernel(T* __restrict__ r, const 
   const bool stop = st >= 0 || !(g > 0.0) || !(delta > 0.0) || !isfinite(g) || !isfinite(delta);
   const double a = stop ? 0.0 : g / delta;
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+  for (int64_t i = (int64_t)bid * kBlock + threadIdx.x; i < m; i += (int64_t)nblk * kBlock) {
     T t = r[i];
     if (a != 0.0) {
       t = (T)((double)t - a * (double)q[i]);
@@ -72,8 +76,8 @@ __global__ void __launch_bounds__(kBlock) upd_r_kernel(T* __restrict__ r, const 
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) {
-    part_r[blockIdx.x] = acc;
-    if (blockIdx.x == 0) {
+    part_r[bid] = acc;
+    if (bid == 0) {
       *alpha_k = a;
       if (stop && st < 0) *status = k;
     }
@@ -83,13 +87,12 @@ __global__ void __launch_bounds__(kBlock) upd_r_kernel(T* __restrict__ r, const 
 // gamma_{k+1} = ||s||^2, beta = gamma_{k+1} / gamma_k (0 at the start or once
 // stopped), p = s + beta p, q = 0, history row k + 1, partial sums of ||p||^2.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) dir_kernel(T* __restrict__ p, const T* __restrict__ s, int64_t np,
-                                                     T* __restrict__ q, int64_t m,
-                                                     const double* __restrict__ part_s, int gs,
-                                                     const double* __restrict__ part_x, int gx,
-                                                     const double* __restrict__ part_r, int gr, double lambda,
-                                                     double* __restrict__ gamma, int k, const int* __restrict__ status,
-                                                     double* __restrict__ hist, double* __restrict__ part_p) {
+__device__ __forceinline__ void dir_body(int bid, int nblk, T* __restrict__ p, const T* __restrict__ s, int64_t np,
+                                         T* __restrict__ q, int64_t m, const double* __restrict__ part_s, int gs,
+                                         const double* __restrict__ part_x, int gx, const double* __restrict__ part_r,
+                                         int gr, double lambda, double* __restrict__ gamma, int k,
+                                         const int* __restrict__ status, double* __restrict__ hist,
+                                         double* __restrict__ part_p) {
   __shared__ double red[4];
   const double ss = sum_partials(part_s, gs, red);
   const double xx = sum_partials(part_x, gx, red);
@@ -101,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) dir_kernel(T* __restrict__ p, const T*
   }
   double acc = 0.0;
   const int64_t n = np > m ? np : m;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  for (int64_t i = (int64_t)bid * kBlock + threadIdx.x; i < n; i += (int64_t)nblk * kBlock) {
     if (i < np) {
       const T t = (T)((double)s[i] + (beta != 0.0 ? beta * (double)p[i] : 0.0));
       p[i] = t;
@@ -111,8 +114,8 @@ __global__ void __launch_bounds__(kBlock) dir_kernel(T* __restrict__ p, const T*
   }
   acc = block_sum(acc, red);
   if (threadIdx.x == 0) {
-    part_p[blockIdx.x] = acc;
-    if (blockIdx.x == 0) {
+    part_p[bid] = acc;
+    if (bid == 0) {
       gamma[k + 1] = ss;
       if (hist) {
         hist[3 * (k + 1) + 0] = sqrt(rr);
@@ -121,6 +124,82 @@ __global__ void __launch_bounds__(kBlock) dir_kernel(T* __restrict__ p, const T*
       }
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) init_r_kernel(T* __restrict__ r, const T* __restrict__ y, const T* __restrict__ q,
+                                                        int64_t m, double* __restrict__ part_r, int* __restrict__ status,
+                                                        double* __restrict__ alpha0) {
+  init_r_body<T>(blockIdx.x, gridDim.x, r, y, q, m, part_r, status, alpha0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) upd_r_kernel(T* __restrict__ r, const T* __restrict__ q, int64_t m,
+                                                       const double* __restrict__ part_q, int gq,
+                                                       const double* __restrict__ part_p, int gp, double lambda,
+                                                       const double* __restrict__ gamma_k, double* __restrict__ alpha_k,
+                                                       int* __restrict__ status, int k, double* __restrict__ part_r) {
+  upd_r_body<T>(blockIdx.x, gridDim.x, r, q, m, part_q, gq, part_p, gp, lambda, gamma_k, alpha_k, status, k, part_r);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) dir_kernel(T* __restrict__ p, const T* __restrict__ s, int64_t np,
+                                                     T* __restrict__ q, int64_t m,
+                                                     const double* __restrict__ part_s, int gs,
+                                                     const double* __restrict__ part_x, int gx,
+                                                     const double* __restrict__ part_r, int gr, double lambda,
+                                                     double* __restrict__ gamma, int k, const int* __restrict__ status,
+                                                     double* __restrict__ hist, double* __restrict__ part_p) {
+  dir_body<T>(blockIdx.x, gridDim.x, p, s, np, q, m, part_s, gs, part_x, gx, part_r, gr, lambda, gamma, k, status, hist,
+              part_p);
+}
+
+// ------------------------------------------------------------------ batches
+// Frame f's state: status[f], gamma and alpha at f * astride, history at
+// f * hstride; vectors at the frame's packed offsets.
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) init_r_batched(const FrameDesc* __restrict__ B, int nf, T* __restrict__ r,
+                                                         const T* __restrict__ y, const T* __restrict__ q,
+                                                         double* __restrict__ part_r, int* __restrict__ status,
+                                                         double* __restrict__ alpha, int astride) {
+  const int g = blockIdx.x;
+  const FrameDesc& F = B[find_frame<&FrameDesc::b_m>(B, nf, g)];
+  const int64_t m = (int64_t)F.op.S * F.op.K;
+  init_r_body<T>(g - F.b_m, F.n_m, r + F.yo, y + F.yo, q ? q + F.yo : nullptr, m, part_r + F.b_m, status + F.frame,
+                 alpha + (size_t)F.frame * astride);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) upd_r_batched(const FrameDesc* __restrict__ B, int nf, T* __restrict__ r,
+                                                        const T* __restrict__ q, const double* __restrict__ part_q,
+                                                        const double* __restrict__ part_p, double lambda,
+                                                        const double* __restrict__ gamma, double* __restrict__ alpha,
+                                                        int astride, int* __restrict__ status, int k,
+                                                        double* __restrict__ part_r) {
+  const int g = blockIdx.x;
+  const FrameDesc& F = B[find_frame<&FrameDesc::b_m>(B, nf, g)];
+  const int64_t m = (int64_t)F.op.S * F.op.K;
+  const size_t a0 = (size_t)F.frame * astride;
+  upd_r_body<T>(g - F.b_m, F.n_m, r + F.yo, q + F.yo, m, part_q + F.s_ga, F.n_ga > 0 ? F.n_ga : 1, part_p + F.b_p,
+                F.n_p, lambda, gamma + a0 + k, alpha + a0 + k + 1, status + F.frame, k, part_r + F.b_m);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) dir_batched(const FrameDesc* __restrict__ B, int nf, T* __restrict__ p,
+                                                      const T* __restrict__ s, const double* __restrict__ part_s,
+                                                      const double* __restrict__ part_x,
+                                                      const double* __restrict__ part_r, double lambda,
+                                                      double* __restrict__ gamma, int astride, int k,
+                                                      const int* __restrict__ status, double* __restrict__ hist,
+                                                      int hstride, double* __restrict__ part_p) {
+  const int g = blockIdx.x;
+  const FrameDesc& F = B[find_frame<&FrameDesc::b_p>(B, nf, g)];
+  const int64_t np = (int64_t)F.op.nx * F.op.ny * F.op.nz;
+  const int gs = F.n_bp > 0 ? F.n_bp : 1;
+  dir_body<T>(g - F.b_p, F.n_p, p + F.xo, s + F.xo, np, (T*)nullptr, 0, part_s + F.s_bp, gs, part_x + F.s_bp, gs,
+              part_r + F.b_m, F.n_m, lambda, gamma + (size_t)F.frame * astride, k, status + F.frame,
+              hist ? hist + (size_t)F.frame * hstride : nullptr, part_p + F.b_p);
 }
 
 hipError_t launch_fill(pa_dtype dt, void* p, int64_t n, hipStream_t st) {
@@ -168,6 +247,47 @@ hipError_t launch_dir(pa_dtype dt, void* p, const void* s, int64_t np, void* q, 
     dir_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(p), static_cast<const double*>(s), np,
                                              static_cast<double*>(q), m, part_s, gs, part_x, gx, part_r, gr, lambda,
                                              gamma, k, status, hist, part_p);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_r_batched(const BatchLaunch& L, void* r, const void* y, const void* q, double* part_r,
+                                 int* status, double* alpha, int astride, hipStream_t st) {
+  if (L.dtype == PA_F32)
+    init_r_batched<float><<<L.m_grid, kBlock, 0, st>>>(L.table, L.nf, static_cast<float*>(r),
+                                                       static_cast<const float*>(y), static_cast<const float*>(q),
+                                                       part_r, status, alpha, astride);
+  else
+    init_r_batched<double><<<L.m_grid, kBlock, 0, st>>>(L.table, L.nf, static_cast<double*>(r),
+                                                        static_cast<const double*>(y), static_cast<const double*>(q),
+                                                        part_r, status, alpha, astride);
+  return hipGetLastError();
+}
+
+hipError_t launch_upd_r_batched(const BatchLaunch& L, void* r, const void* q, const double* part_q,
+                                const double* part_p, double lambda, const double* gamma, double* alpha, int astride,
+                                int* status, int k, double* part_r, hipStream_t st) {
+  if (L.dtype == PA_F32)
+    upd_r_batched<float><<<L.m_grid, kBlock, 0, st>>>(L.table, L.nf, static_cast<float*>(r),
+                                                      static_cast<const float*>(q), part_q, part_p, lambda, gamma,
+                                                      alpha, astride, status, k, part_r);
+  else
+    upd_r_batched<double><<<L.m_grid, kBlock, 0, st>>>(L.table, L.nf, static_cast<double*>(r),
+                                                       static_cast<const double*>(q), part_q, part_p, lambda, gamma,
+                                                       alpha, astride, status, k, part_r);
+  return hipGetLastError();
+}
+
+hipError_t launch_dir_batched(const BatchLaunch& L, void* p, const void* s, const double* part_s, const double* part_x,
+                              const double* part_r, double lambda, double* gamma, int astride, int k,
+                              const int* status, double* hist, int hstride, double* part_p, hipStream_t st) {
+  if (L.dtype == PA_F32)
+    dir_batched<float><<<L.p_grid, kBlock, 0, st>>>(L.table, L.nf, static_cast<float*>(p),
+                                                    static_cast<const float*>(s), part_s, part_x, part_r, lambda,
+                                                    gamma, astride, k, status, hist, hstride, part_p);
+  else
+    dir_batched<double><<<L.p_grid, kBlock, 0, st>>>(L.table, L.nf, static_cast<double*>(p),
+                                                     static_cast<const double*>(s), part_s, part_x, part_r, lambda,
+                                                     gamma, astride, k, status, hist, hstride, part_p);
   return hipGetLastError();
 }
 

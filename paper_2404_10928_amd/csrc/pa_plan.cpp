@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <limits>
 
 namespace pa {
@@ -216,6 +217,114 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.vec_p = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.fwd = off; off = align_up(off + std::max<size_t>(plan.fwd_scratch, 256), A);
+  L.total = off;
+  return L;
+}
+
+pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, BatchPlan* bp,
+                          std::string* msg) {
+  if (!bp) return fail(msg, PA_ERR_INVALID_ARGUMENT, "batch plan pointer is NULL");
+  if (n_frames < 1) return fail(msg, PA_ERR_INVALID_ARGUMENT, "a batch needs at least one frame");
+  if (!frames) return fail(msg, PA_ERR_INVALID_ARGUMENT, "frame array is NULL");
+  if (n_frames > (1 << 16)) return fail(msg, PA_ERR_UNSUPPORTED, "more than 65536 frames");
+  BatchPlan B;
+  B.nf = n_frames;
+  B.dtype = dtype;
+  B.plans.resize(n_frames);
+  for (int i = 0; i < n_frames; ++i) {
+    std::string m;
+    pa_status st = make_plan(&frames[i], dtype, &B.plans[i], &m);
+    if (st != PA_OK) {
+      if (msg) *msg = "frame " + std::to_string(i) + ": " + m;
+      return st;
+    }
+    if (i > 0 && frames[i].ndim != frames[0].ndim)
+      return fail(msg, PA_ERR_INVALID_ARGUMENT, "every frame of a batch must have the same ndim");
+  }
+  B.ndim = frames[0].ndim;
+  B.elem = B.plans[0].elem;
+  // packed buffers in caller order
+  B.xoff.assign(n_frames + 1, 0);
+  B.yoff.assign(n_frames + 1, 0);
+  for (int i = 0; i < n_frames; ++i) {
+    B.xoff[i + 1] = B.xoff[i] + B.plans[i].P;
+    B.yoff[i + 1] = B.yoff[i] + B.plans[i].M;
+  }
+  B.P_total = B.xoff[n_frames];
+  B.M_total = B.yoff[n_frames];
+  if (B.P_total > std::numeric_limits<int32_t>::max() || B.M_total > std::numeric_limits<int32_t>::max() * 4ll)
+    return fail(msg, PA_ERR_UNSUPPORTED, "packed batch too large");
+  // largest frames first, so the long work-groups start early (stable for ties)
+  std::vector<int> order(n_frames);
+  for (int i = 0; i < n_frames; ++i) order[i] = i;
+  auto work = [&](int i) { return (double)B.plans[i].P * (double)B.plans[i].op.S; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  int64_t bbp = 0, bfp = 0, bga = 0, bm = 0, bpp = 0, sbp = 0, sga = 0;
+  size_t scr = 0;
+  B.table.resize(n_frames);
+  for (int j = 0; j < n_frames; ++j) {
+    const int i = order[j];
+    const Plan& pl = B.plans[i];
+    FrameDesc& F = B.table[j];
+    std::memset(&F, 0, sizeof(F));
+    F.op = pl.op;
+    F.frame = i;
+    F.xo = B.xoff[i];
+    F.yo = B.yoff[i];
+    F.b_bp = (int32_t)bbp; F.n_bp = pl.bp_grid; bbp += F.n_bp;
+    F.b_fp = (int32_t)bfp; F.n_fp = pl.fp_grid; bfp += F.n_fp;
+    F.b_ga = (int32_t)bga; F.n_ga = pl.M > 0 ? pl.op.S * pl.op.nseg : 0; bga += F.n_ga;
+    F.b_m = (int32_t)bm; F.n_m = blas_grid(pl.M); bm += F.n_m;
+    F.b_p = (int32_t)bpp; F.n_p = blas_grid(pl.P); bpp += F.n_p;
+    F.s_bp = (int32_t)sbp; sbp += std::max(F.n_bp, 1);
+    F.s_ga = (int32_t)sga; sga += std::max(F.n_ga, 1);
+    F.scr = (int64_t)scr;
+    F.scr_tab = (int64_t)(scr + pl.klo_tab_off);
+    if (pl.fp_grid > 0) scr = align_up(scr + pl.fwd_scratch, 256);
+    B.frac = B.frac || pl.op.t0f != 0.0f;
+    B.bp_lds = std::max(B.bp_lds, pl.bp_lds);
+    B.fp_lds = std::max(B.fp_lds, pl.fp_lds);
+    B.gather_lds = std::max(B.gather_lds, pl.gather_lds);
+  }
+  const int64_t lim = std::numeric_limits<int32_t>::max();
+  if (bbp > lim || bfp > lim || bga > lim || bm > lim || bpp > lim || sbp > lim || sga > lim)
+    return fail(msg, PA_ERR_UNSUPPORTED, "batch needs more than 2^31-1 work-groups in one launch");
+  B.bp_grid = (int)bbp;
+  B.fp_grid = (int)bfp;
+  B.gather_grid = (int)bga;
+  B.m_grid = (int)bm;
+  B.p_grid = (int)bpp;
+  B.bp_slots = (int)sbp;
+  B.ga_slots = (int)sga;
+  B.fwd_scratch = std::max<size_t>(scr, 256);
+  *bp = std::move(B);
+  return PA_OK;
+}
+
+BatchLayout batch_layout(const BatchPlan& B, int32_t iters, bool cg) {
+  BatchLayout L{};
+  const size_t A = 256;
+  size_t off = 0;
+  L.table = off; off = align_up(off + sizeof(FrameDesc) * (size_t)B.nf, A);
+  L.fwd = off; off = align_up(off + B.fwd_scratch, A);
+  if (!cg) {
+    L.total = off;
+    return L;
+  }
+  L.astride = std::max(iters, 0) + 2;
+  const size_t nf = (size_t)B.nf;
+  L.status = off; off = align_up(off + sizeof(int) * nf, A);
+  L.gamma = off; off = align_up(off + sizeof(double) * nf * L.astride, A);
+  L.alpha = off; off = align_up(off + sizeof(double) * nf * L.astride, A);
+  L.part_q = off; off = align_up(off + sizeof(double) * B.ga_slots, A);
+  L.part_r = off; off = align_up(off + sizeof(double) * B.m_grid, A);
+  L.part_s = off; off = align_up(off + sizeof(double) * B.bp_slots, A);
+  L.part_x = off; off = align_up(off + sizeof(double) * B.bp_slots, A);
+  L.part_p = off; off = align_up(off + sizeof(double) * B.p_grid, A);
+  L.vec_r = off; off = align_up(off + B.elem * (size_t)std::max<int64_t>(B.M_total, 1), A);
+  L.vec_q = off; off = align_up(off + B.elem * (size_t)std::max<int64_t>(B.M_total, 1), A);
+  L.vec_s = off; off = align_up(off + B.elem * (size_t)std::max<int64_t>(B.P_total, 1), A);
+  L.vec_p = off; off = align_up(off + B.elem * (size_t)std::max<int64_t>(B.P_total, 1), A);
   L.total = off;
   return L;
 }

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "pa.h"
 
@@ -116,23 +117,54 @@ struct Plan {
 pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg);
 
 // One frame of a batch as the batched kernels see it (device table, sorted
-// by work per block, largest first).  Block ranges are those of each batched
-// launch; partial sums are stored at the frame's first block + local index,
-// so a frame's sums are formed in the same order as in a single-frame call.
+// by work, largest first).  Block ranges [b_*, b_* + n_*) are those of each
+// batched launch; partial sums go to the frame's own slot range, at the same
+// local index as in a single-frame call, so every frame's sums are formed in
+// the same order as when it is solved alone.
 struct FrameDesc {
   OpParams op;
   int64_t xo, yo;      // element offsets of the frame's image / traces in the packed buffers
   int64_t scr;         // byte offset of the frame's forward partial rows in the scratch area
   int64_t scr_tab;     // byte offset of the frame's window-start table in the scratch area
-  int32_t b_bp, n_bp;  // adjoint blocks
-  int32_t b_fp, n_fp;  // forward pass-1 blocks
-  int32_t b_ga, n_ga;  // forward gather blocks
-  int32_t b_m, n_m;    // BLAS blocks over the frame's S*K samples
-  int32_t b_p, n_p;    // BLAS blocks over the frame's pixels
+  int32_t b_bp, n_bp;  // adjoint blocks (n_bp = 0 without pixels)
+  int32_t b_fp, n_fp;  // forward pass-1 blocks (0 when the frame is empty)
+  int32_t b_ga, n_ga;  // forward gather blocks (S * nseg whenever S * K > 0)
+  int32_t b_m, n_m;    // BLAS blocks over the frame's S*K samples (>= 1)
+  int32_t b_p, n_p;    // BLAS blocks over the frame's pixels (>= 1)
+  int32_t s_bp;        // first slot of the frame's adjoint partials (max(n_bp, 1) slots)
+  int32_t s_ga;        // first slot of the frame's gather partials (max(n_ga, 1) slots)
   int32_t frame;       // position in the caller's frame order
   int32_t pad;
 };
 
+// Host plan of a batch: per-frame plans (caller order), the device table
+// (work order) and the grid and buffer totals.
+struct BatchPlan {
+  int nf = 0;
+  int ndim = 2;
+  pa_dtype dtype = PA_F32;
+  size_t elem = 4;
+  bool frac = false;
+  std::vector<Plan> plans;        // caller order
+  std::vector<FrameDesc> table;   // work order (largest first)
+  std::vector<int64_t> xoff, yoff;  // caller order, nf + 1 prefix offsets (elements)
+  int bp_grid = 0, fp_grid = 0, gather_grid = 0, m_grid = 0, p_grid = 0;
+  int bp_slots = 0, ga_slots = 0;
+  size_t bp_lds = 0, fp_lds = 0, gather_lds = 0;
+  size_t fwd_scratch = 0;
+  int64_t P_total = 0, M_total = 0;
+};
+
+pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, BatchPlan* bp,
+                          std::string* msg);
+
+// Workspace of batched calls: the device frame table, the forward scratch
+// and (cg) the per-frame CGLS state for `iters` iterations, partials and vectors.
+struct BatchLayout {
+  size_t table, status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, fwd, total;
+  int astride;   // doubles per frame in gamma and alpha (iters + 2)
+};
+BatchLayout batch_layout(const BatchPlan& bp, int32_t iters, bool cg);
 
 // Sizes of the BLAS-1 grids (fixed per vector length so every reduction runs
 // in the same order every time).

@@ -230,3 +230,126 @@ def cgls(y: torch.Tensor, geom, iters: int, lam: float, x0: torch.Tensor | None 
         solver.solve(y.contiguous(), x, x0_zero=False)
     stop = solver.stop_iteration()
     return x, solver.history.clone(), stop
+
+
+class Batch:
+    """Many frames of uneven size under one plan: one launch per step for all frames.
+
+    geoms: frame geometries (objects accepted by DeviceGeometry), all with the
+    same ndim.  Packed buffers hold the frames one after another in the given
+    order; `x_offsets` / `y_offsets` (length n + 1) give each frame's element
+    range, and pack_x / unpack_x / pack_y / unpack_y convert from and to
+    per-frame tensors.
+    """
+
+    def __init__(self, geoms, dtype: torch.dtype = torch.float32, device=None):
+        self.geoms = [as_device_geometry(g, device) for g in geoms]
+        if not self.geoms:
+            raise ValueError("a batch needs at least one frame")
+        self.device = self.geoms[0].device
+        self.dtype = dtype
+        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._structs = (_lib.PaGeometry * len(self.geoms))(*[g.c_struct() for g in self.geoms])
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(self._lib.pa_batch_create(self._structs, len(self.geoms), self._code, ctypes.byref(h)))
+        self._h = h
+        n = len(self.geoms)
+        xo = (ctypes.c_int64 * (n + 1))()
+        yo = (ctypes.c_int64 * (n + 1))()
+        _lib.check(self._lib.pa_batch_offsets(self._h, xo, yo))
+        self.x_offsets = [int(v) for v in xo]
+        self.y_offsets = [int(v) for v in yo]
+        self._ws = None
+        self._ws_cg = {}
+        self.history = None
+
+    def __len__(self):
+        return len(self.geoms)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            torch.cuda.synchronize(self.device)
+            self._lib.pa_batch_destroy(h)
+            self._h = None
+
+    # packing helpers (torch copies; no arithmetic)
+    def pack_x(self, xs):
+        return torch.cat([x.reshape(-1).to(self.dtype) for x in xs]).contiguous()
+
+    def pack_y(self, ys):
+        return torch.cat([y.reshape(-1).to(self.dtype) for y in ys]).contiguous()
+
+    def unpack_x(self, x):
+        return [x[self.x_offsets[i]:self.x_offsets[i + 1]].reshape(g.image_shape) for i, g in enumerate(self.geoms)]
+
+    def unpack_y(self, y):
+        return [y[self.y_offsets[i]:self.y_offsets[i + 1]].reshape(g.data_shape) for i, g in enumerate(self.geoms)]
+
+    def _workspace(self):
+        if self._ws is None:
+            n = self._lib.pa_batch_workspace_bytes(self._h)
+            self._ws = torch.empty(max(int(n), 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _check(self, t, n, name):
+        _check_tensor(t, n, name)
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}")
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Packed y := A x, frame by frame."""
+        self._check(x, self.x_offsets[-1], "x")
+        if out is None:
+            out = torch.empty(self.y_offsets[-1], dtype=self.dtype, device=self.device)
+        self._check(out, self.y_offsets[-1], "y")
+        ws = self._workspace()
+        _lib.check(self._lib.pa_batch_forward(self._h, x.data_ptr() or None, out.data_ptr() or None, ws.data_ptr(),
+                                              ws.numel(), _stream(self.device)))
+        return out
+
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Packed x := A^T y, frame by frame."""
+        self._check(y, self.y_offsets[-1], "y")
+        if out is None:
+            out = torch.empty(self.x_offsets[-1], dtype=self.dtype, device=self.device)
+        self._check(out, self.x_offsets[-1], "x")
+        ws = self._workspace()
+        _lib.check(self._lib.pa_batch_adjoint(self._h, y.data_ptr() or None, out.data_ptr() or None, ws.data_ptr(),
+                                              ws.numel(), _stream(self.device)))
+        return out
+
+    def cgls(self, y: torch.Tensor, iters: int, lam: float, x: torch.Tensor | None = None, x0_zero: bool = True,
+             graph: bool = True) -> torch.Tensor:
+        """CGLS on every frame; x (packed) is the start (unless x0_zero) and the result.
+        self.history becomes [n_frames][iters + 1][3] (||r_k||, ||s_k||, F_k) on the device."""
+        iters = int(iters)
+        self._check(y, self.y_offsets[-1], "y")
+        if x is None:
+            x = torch.empty(self.x_offsets[-1], dtype=self.dtype, device=self.device)
+            x0_zero = True
+        self._check(x, self.x_offsets[-1], "x")
+        ws = self._ws_cg.get(iters)
+        if ws is None:
+            n = self._lib.pa_batch_cgls_workspace_bytes(self._h, iters)
+            if n == 0:
+                raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
+            ws = self._ws_cg[iters] = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        if self.history is None or self.history.shape != (len(self), iters + 1, 3):
+            self.history = torch.zeros((len(self), iters + 1, 3), dtype=torch.float64, device=self.device)
+        flags = (_lib.PA_X0_ZERO if x0_zero else 0) | (_lib.PA_USE_GRAPH if graph else 0)
+        _lib.check(self._lib.pa_batch_cgls_solve(self._h, y.data_ptr() or None, x.data_ptr() or None, iters,
+                                                 float(lam), flags, ws.data_ptr(), ws.numel(),
+                                                 self.history.data_ptr(), _stream(self.device)))
+        self._last_iters = iters
+        return x
+
+    def stop_iterations(self) -> list:
+        """Per frame: the iteration its last solve stopped at, or -1 (synchronises)."""
+        torch.cuda.synchronize(self.device)
+        iters = self._last_iters
+        out = (ctypes.c_int32 * len(self))()
+        _lib.check(self._lib.pa_batch_stop_iterations(self._h, self._ws_cg[iters].data_ptr(), iters, out),
+                   allow=(_lib.PA_OK, _lib.PA_ERR_BREAKDOWN))
+        return [int(v) for v in out]

@@ -117,3 +117,61 @@ def test_pointer_and_argument_checks_on_host(lib):
     assert solve(args(wsb=ws - 1)) == 3
     stop = ctypes.c_int32()
     assert lib.pa_cgls_stop_iteration(None, ctypes.byref(stop)) == 1
+
+
+def batch_lib(lib):
+    vp = ctypes.c_void_p
+    gp = ctypes.POINTER(Geom)
+    lib.pa_batch_create.argtypes = [gp, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.pa_batch_destroy.argtypes = [vp]
+    lib.pa_batch_offsets.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.pa_batch_workspace_bytes.argtypes = [vp]
+    lib.pa_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_batch_cgls_workspace_bytes.argtypes = [vp, ctypes.c_int32]
+    lib.pa_batch_cgls_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_batch_forward.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pa_batch_cgls_solve.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32, vp,
+                                        ctypes.c_size_t, vp, vp]
+    return lib
+
+
+def test_batch_planning_on_host(lib):
+    lib = batch_lib(lib)
+    frames = (Geom * 3)(good(), good(), good())
+    frames[1].nx, frames[1].n_sensors, frames[1].n_samples = 100, 17, 450
+    frames[2].ny, frames[2].dt = 7, 40e-9
+    h = ctypes.c_void_p()
+    assert lib.pa_batch_create(frames, 3, 0, ctypes.byref(h)) == 0 and h.value
+    xo = (ctypes.c_int64 * 4)()
+    yo = (ctypes.c_int64 * 4)()
+    assert lib.pa_batch_offsets(h, xo, yo) == 0
+    P = [64 * 48, 100 * 48, 64 * 7]
+    M = [32 * 300, 17 * 450, 32 * 300]
+    assert list(xo) == [0, P[0], P[0] + P[1], sum(P)]
+    assert list(yo) == [0, M[0], M[0] + M[1], sum(M)]
+    n_op = lib.pa_batch_workspace_bytes(h)
+    n_cg = lib.pa_batch_cgls_workspace_bytes(h, 20)
+    assert n_op > 0 and n_cg >= n_op + 4 * 2 * (sum(P) + sum(M))
+    # workspace and buffer checks fail on the host, before any HIP call
+    assert lib.pa_batch_forward(h, 1 << 20, 1 << 28, None, 0, None) == 3
+    assert lib.pa_batch_forward(h, 1 << 20, 1 << 28, (1 << 32) + 16, n_op, None) == 3
+    assert lib.pa_batch_forward(h, 1 << 20, 1 << 28, 1 << 32, n_op - 1, None) == 3
+    assert lib.pa_batch_forward(h, None, 1 << 28, 1 << 32, n_op, None) == 1
+    assert lib.pa_batch_cgls_solve(h, 1 << 28, 1 << 20, 5, -1.0, 1, 1 << 32, n_cg, None, None) == 1
+    assert lib.pa_batch_cgls_solve(h, 1 << 28, 1 << 20, 5, 1e-3, 8, 1 << 32, n_cg, None, None) == 1
+    assert lib.pa_batch_destroy(h) == 0
+
+
+def test_batch_rejects_bad_frames_on_host(lib):
+    lib = batch_lib(lib)
+    h = ctypes.c_void_p()
+    frames = (Geom * 2)(good(), good())
+    assert lib.pa_batch_create(frames, 0, 0, ctypes.byref(h)) == 1
+    frames[1].dt = -1.0
+    assert lib.pa_batch_create(frames, 2, 0, ctypes.byref(h)) == 1
+    assert b"frame 1" in lib.pa_last_error()
+    frames[1] = good()
+    frames[1].ndim, frames[1].nz = 3, 4
+    frames[1].sensors = 4096 * 3
+    assert lib.pa_batch_create(frames, 2, 0, ctypes.byref(h)) == 1
+    assert b"ndim" in lib.pa_last_error()
