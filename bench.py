@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle CGLS iterations timed on the host")
     ap.add_argument("--quick", action="store_true", help="skip operator and CPU legs (profiling runs)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched-frames and 3D legs")
     ap.add_argument("--calib-copy-mib", type=int, default=64,
                     help="size of a plain device copy run once (counter calibration for profiling runs)")
     return ap.parse_args()
@@ -222,8 +223,90 @@ def main():
             print(f"[bench] parity A {e_a:.2e} A^T {e_at:.2e}; oracle {it} its in {te - td:.1f} s",
                   file=sys.stderr, flush=True)
 
+    if not args.quick and not args.no_extras:
+        out["batched_frames"] = batched_leg(pa, torch, dev)
+        out["volume_3d"] = volume_leg(pa, torch, dev)
+
     print(json.dumps(out))
     return 0
+
+
+def _sync_time(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def batched_leg(pa, torch, dev):
+    """64 uneven frames (images 128-512, 64-512 sensors, 512-2048 samples),
+    50 CGLS iterations: one batched graph replay against 64 single-frame
+    graph replays, with the largest per-frame iterate difference."""
+    from synth import add_noise, make_config
+    w = make_config("C4")
+    geoms = [pa.DeviceGeometry(g, dev) for g in w.geoms]
+    b = pa.Batch(geoms, torch.float32, dev)
+    xp = b.pack_x([torch.from_numpy(x.astype(np.float32)).to(dev) for x in w.x_true])
+    yc = b.unpack_y(b.forward(xp))
+    ys = [torch.from_numpy(add_noise(y.double().cpu().numpy(), w.noise_rel, w.noise_seeds[i]).astype(np.float32)).to(dev)
+          for i, y in enumerate(yc)]
+    yp = b.pack_y(ys)
+    xb = torch.empty(b.x_offsets[-1], dtype=torch.float32, device=dev)
+    b.cgls(yp, w.iters, w.lam, xb)
+    t_b = _sync_time(torch, lambda: b.cgls(yp, w.iters, w.lam, xb), 3)
+    solvers = [pa.CglsSolver(g, torch.float32, w.iters, w.lam, graph=True, device=dev) for g in geoms]
+    xs = [torch.empty(g.image_shape, dtype=torch.float32, device=dev) for g in geoms]
+    def loop():
+        for sv, y, x in zip(solvers, ys, xs):
+            sv.solve(y, x)
+    loop()
+    t_s = _sync_time(torch, loop, 2)
+    diffs = [float(torch.linalg.norm((a.reshape(-1) - c.reshape(-1)).double()) / max(float(torch.linalg.norm(c.double())), 1e-300))
+             for a, c in zip(b.unpack_x(xb), xs)]
+    n = len(geoms)
+    pairs = sum(g.n_pixels * g.n_sensors for g in geoms)
+    print(f"[bench] batched {n} frames: {t_b * 1e3:.2f} ms per {w.iters}-iteration solve; "
+          f"single-frame loop {t_s * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    return {"workload": f"{n} frames of 128-512 px square images, 64-512 sensors, 512-2048 samples, "
+                        f"{w.iters} CGLS iterations, FP32", "pairs_per_apply": pairs,
+            "frame_iterations_per_s_batched": n * w.iters / t_b,
+            "frame_iterations_per_s_single_frame_loop": n * w.iters / t_s,
+            "speedup": t_s / t_b, "max_rel_l2_batched_vs_single": max(diffs)}
+
+
+def volume_leg(pa, torch, dev):
+    """128^3 voxels, 1024-sensor hemisphere, 2048 samples, 30 CGLS iterations
+    in FP32 (FP64 reductions) and in FP64, timed, with their iterate gap."""
+    from synth import add_noise, make_config
+    w = make_config("C5")
+    g = pa.DeviceGeometry(w.geom, dev)
+    x_true = torch.from_numpy(w.x.astype(np.float32)).to(dev)
+    y32 = torch.from_numpy(add_noise(pa.forward(x_true, g).double().cpu().numpy(), w.noise_rel,
+                                     w.noise_seeds[0]).astype(np.float32)).to(dev)
+    res = {"workload": "128^3 voxels (0.1 mm), 1024-sensor Fibonacci hemisphere at 20 mm, 2048 samples at 20 ns, "
+                       f"{w.iters} CGLS iterations"}
+    xs = {}
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        sv = pa.CglsSolver(g, dt, w.iters, w.lam, graph=True, device=dev)
+        y = y32.to(dt)
+        x = torch.empty(g.image_shape, dtype=dt, device=dev)
+        sv.solve(y, x)
+        t = _sync_time(torch, lambda: sv.solve(y, x), 2)
+        op = pa.Operator(g, dt, dev)
+        yo = torch.empty_like(y)
+        xo = torch.empty_like(x)
+        t_a = _sync_time(torch, lambda: op.forward_(x, yo), 5)
+        t_at = _sync_time(torch, lambda: op.adjoint_(y, xo), 5)
+        res[name] = {"cgls_iterations_per_s": w.iters / t, "us_per_A": t_a * 1e6, "us_per_AT": t_at * 1e6,
+                     "final_F": float(sv.history[-1, 2])}
+        xs[name] = x.double()
+    res["iterate_rel_l2_f32_vs_f64"] = float(torch.linalg.norm(xs["f32"] - xs["f64"]) / torch.linalg.norm(xs["f64"]))
+    res["final_F_rel_f32_vs_f64"] = abs(res["f32"]["final_F"] / res["f64"]["final_F"] - 1)
+    print(f"[bench] 3D: f32 {res['f32']['cgls_iterations_per_s']:.1f} it/s, f64 {res['f64']['cgls_iterations_per_s']:.1f} it/s, "
+          f"iterate gap {res['iterate_rel_l2_f32_vs_f64']:.2e}", file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":

@@ -176,6 +176,28 @@ pa_status pa_batch_cgls_solve(pa_batch* b, const void* y, void* x, int32_t iters
  * device-to-host copy. */
 pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int32_t iters, int32_t* stop);
 
+/* ------------------------------------------------------------------ tuning
+ * The planner picks the forward operator's tile (base tiles per forward
+ * tile) and the adjoint's sensor chunk (from an LDS budget) by rule.
+ * pa_autotune times each candidate tiling of both operators on this
+ * geometry and records the fastest in a process-wide table keyed by shape
+ * (ndim, dtype, nx, ny, nz, S, K and h / (c dt)); every later call on a
+ * geometry of that shape, batches included, plans with the recorded tiling.
+ * Tilings change only the order of floating-point sums, not the operator.
+ * x, y: device buffers of the geometry's image and trace sizes, used as
+ * scratch (their contents are overwritten).  Synchronises the stream.  May
+ * allocate the forward operator's internal scratch (as pa_forward does). */
+typedef struct {
+  int32_t fwd_tile[3];     /* base tiles per forward tile, per axis (0: no forward work) */
+  int32_t adj_lds_bytes;   /* adjoint LDS budget that sets its sensor chunk (0: no adjoint work) */
+  double fwd_us, adj_us;   /* measured time per apply of the chosen tilings */
+} pa_tuning;
+
+pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, void* hip_stream, pa_tuning* out);
+
+/* Forgets every recorded tiling (later plans use the planner's rules). */
+pa_status pa_tuning_clear(void);
+
 /* Message for the last failing call on this thread ("" if none).  Valid until
  * the next pa_* call on the same thread. */
 const char* pa_last_error(void);

@@ -31,7 +31,12 @@ PA_USE_GRAPH = 2
 EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspace_bytes", "pa_cgls_solve",
            "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version", "pa_batch_create", "pa_batch_destroy",
            "pa_batch_offsets", "pa_batch_workspace_bytes", "pa_batch_cgls_workspace_bytes", "pa_batch_forward",
-           "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations"]
+           "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations", "pa_autotune", "pa_tuning_clear"]
+
+
+class PaTuning(ctypes.Structure):
+    _fields_ = [("fwd_tile", ctypes.c_int32 * 3), ("adj_lds_bytes", ctypes.c_int32), ("fwd_us", ctypes.c_double),
+                ("adj_us", ctypes.c_double)]
 
 
 class PaGeometry(ctypes.Structure):
@@ -95,6 +100,10 @@ def load(path: str = LIB_PATH):
     lib.pa_batch_cgls_solve.restype = ctypes.c_int
     lib.pa_batch_stop_iterations.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.pa_batch_stop_iterations.restype = ctypes.c_int
+    lib.pa_autotune.argtypes = [gp, ctypes.c_int, vp, vp, vp, ctypes.POINTER(PaTuning)]
+    lib.pa_autotune.restype = ctypes.c_int
+    lib.pa_tuning_clear.argtypes = []
+    lib.pa_tuning_clear.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -644,4 +644,96 @@ pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int
   return any ? PA_ERR_BREAKDOWN : PA_OK;
 }
 
+pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, void* hip_stream, pa_tuning* out) {
+  g_err.clear();
+  pa::Plan base;
+  pa_status st = plan_or_fail(g, dtype, &base);
+  if (st != PA_OK) return st;
+  if ((st = check_vec(x, base.P, base.elem, "x")) != PA_OK) return st;
+  if ((st = check_vec(y, base.M, base.elem, "y")) != PA_OK) return st;
+  if (overlap(x, base.P * base.elem, y, base.M * base.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PA_HIP(hipEventCreate(&e0), "hipEventCreate");
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_err(he, "hipEventCreate");
+  }
+  auto time_it = [&](auto&& launch, float* us) -> hipError_t {
+    hipError_t e;
+    if ((e = launch()) != hipSuccess) return e;  // warm-up (and first-use attribute setting)
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+    for (int r = 0; r < 3; ++r)
+      if ((e = launch()) != hipSuccess) return e;
+    if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+    *us = ms * 1000.f / 3.f;
+    return hipSuccess;
+  };
+  pa::Tuning best{{0, 0, 0}, 0};
+  float best_f = 3.0e38f, best_a = 3.0e38f;
+  hipError_t err = hipSuccess;
+  // forward tilings
+  if (base.fp_grid > 0) {
+    int cand[8][3];
+    const int nc = pa::fwd_tile_candidates(base.ndim, cand, 8);
+    for (int i = 0; i < nc && err == hipSuccess; ++i) {
+      pa::Tuning t{{cand[i][0], cand[i][1], cand[i][2]}, 0};
+      pa::Plan pl;
+      std::string msg;
+      if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK) continue;
+      if (pl.op.msub[0] != t.fwd_tile[0] || pl.op.msub[1] != t.fwd_tile[1] || pl.op.msub[2] != t.fwd_tile[2])
+        continue;  // did not fit; the planner fell back to its own choice
+      void* scratch = nullptr;
+      if ((err = get_scratch(pl.fwd_scratch, s, &scratch)) != hipSuccess) break;
+      float us = 0.f;
+      err = time_it([&] { return pa::launch_forward(pl, x, y, scratch, nullptr, s); }, &us);
+      if (err == hipSuccess && us < best_f) {
+        best_f = us;
+        for (int a = 0; a < 3; ++a) best.fwd_tile[a] = t.fwd_tile[a];
+      }
+    }
+  }
+  // adjoint LDS budgets
+  if (base.bp_grid > 0 && err == hipSuccess) {
+    size_t cand[8];
+    const int nc = pa::adj_lds_candidates(cand, 8);
+    int last_sc = -1;
+    for (int i = 0; i < nc && err == hipSuccess; ++i) {
+      pa::Tuning t{{0, 0, 0}, (int32_t)cand[i]};
+      pa::Plan pl;
+      std::string msg;
+      if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK) continue;
+      if (pl.op.sc == last_sc) continue;  // same sensor chunk as the previous budget
+      last_sc = pl.op.sc;
+      float us = 0.f;
+      err = time_it([&] { return pa::launch_adjoint(pl, y, x, nullptr, s); }, &us);
+      if (err == hipSuccess && us < best_a) {
+        best_a = us;
+        best.adj_lds = t.adj_lds;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_err(err, "autotune");
+  pa::tune_store(g, dtype, best);
+  if (out) {
+    for (int a = 0; a < 3; ++a) out->fwd_tile[a] = best.fwd_tile[a];
+    out->adj_lds_bytes = best.adj_lds;
+    out->fwd_us = best_f < 3.0e38f ? best_f : 0.0;
+    out->adj_us = best_a < 3.0e38f ? best_a : 0.0;
+  }
+  return PA_OK;
+}
+
+pa_status pa_tuning_clear(void) {
+  g_err.clear();
+  pa::tune_clear();
+  return PA_OK;
+}
+
 }  // extern "C"

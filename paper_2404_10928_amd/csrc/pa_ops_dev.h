@@ -549,24 +549,29 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
     c.BASE += (int)(size_t)hist;  // absolute LDS byte address
     asm volatile("" : "+v"(c.BASE));  // keep "k * 8 + BASE" a single shift-add
     const T* xm = xs + m * kBlock;
-    for (int lz = 0; lz < nlz; ++lz) {
-      for (int ly = 0; ly < nly; ++ly) {
-        const int rowp = (lz * TY + ly) * TX;
+    // Every pixel of the base tile, in order.  Pixels beyond the image edge
+    // have x = 0 (and taps inside the window), so they add zeros.  The next
+    // pixel's constants are read before this pixel's LDS adds are issued, so
+    // the adds never hold up the reads.
+    constexpr int NPIX = TX * TY * TZ;
+    PX pn = pixtab[0];
+    T xn = xm[0];
 #pragma unroll 2
-        for (int lx = 0; lx < nlx; ++lx) {
-          const PX px = pixtab[rowp + lx];
-          const T xp = xm[rowp + lx];
-          int kb;
-          T f, wt;
-          phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
-          const double v = (double)(wt * xp);
-          const double a1 = v * (double)f;
-          const double a0 = v - a1;
-          double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
-          lds_add(bin, a0);
-          lds_add(bin + 1, a1);
-        }
-      }
+    for (int p = 0; p < NPIX; ++p) {
+      const PX px = pn;
+      const T xp = xn;
+      const int pq = p + 1 < NPIX ? p + 1 : p;
+      pn = pixtab[pq];
+      xn = xm[pq];
+      int kb;
+      T f, wt;
+      phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
+      const double v = (double)(wt * xp);
+      const double a1 = v * (double)f;
+      const double a0 = v - a1;
+      double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
+      lds_add(bin, a0);
+      lds_add(bin + 1, a1);
     }
     if constexpr (F32) {
       uint64_t nm = __ballot(near);
@@ -606,28 +611,32 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
   }
   __syncthreads();
 
-  // histogram rows out, row (forward tile, sensor) at ((at * S) + s) * wpa
+  // histogram rows out, row (sensor, forward tile) at ((s * n_atiles) + at) * wpa
   for (int j = wave; j < NS; j += 4) {
     const int sj = chunk * NS + j;
     if (sj >= P.S) break;
-    T* row = rows + ((size_t)at * P.S + sj) * P.wpa;
+    T* row = rows + ((size_t)sj * P.n_atiles + at) * P.wpa;
     for (int i = lane; i < P.wpa; i += 64) row[i] = (T)hist[j * P.wpa + i];
   }
-  if (wave == 0 && s_ok) klo_tab[(size_t)at * P.S + s] = klo_a[lane];
+  if (wave == 0 && s_ok) klo_tab[(size_t)s * P.n_atiles + at] = klo_a[lane];
 }
 
-// A, pass 2: one work-group per (sensor, segment of kseg samples).  Wave w
-// adds the rows of forward tiles w, w+4, ... (in increasing order) into its
-// own LDS copy of the segment; the four copies are then summed in a fixed
-// order, scaled and written to y, with the FP64 partial of ||y||^2.  No
-// atomics: the result is the same on every run.
+// A, pass 2: one work-group per (sensor, segment of kseg <= 256 samples),
+// one sample per lane.  The work-group lists, in increasing order, the
+// forward tiles whose row window overlaps its segment, then every lane adds
+// its sample of those rows in list order in FP64, scales, and writes y, with
+// the FP64 partial of ||y||^2.  No atomics: the result is the same on every
+// run.  Rows and window starts are sensor-major, so one sensor's rows are
+// contiguous.
 template <typename T>
 __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx, const T* __restrict__ rows,
                                             const int* __restrict__ klo_tab, T* __restrict__ y,
                                             double* __restrict__ part_q) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T* tr = reinterpret_cast<T*>(smem);
+  int* list = reinterpret_cast<int*>(smem);               // kGatherChunk tile indices
+  int* lkl = list + kGatherChunk;                          // their window starts
   __shared__ double red[4];
+  __shared__ int wcount[4];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -635,28 +644,78 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
   const int seg = blk - s * P.nseg;
   const int k0 = seg * P.kseg;
   const int kn = min(P.kseg, P.K - k0);
-  for (int i = tid; i < 4 * P.kseg; i += kBlock) tr[i] = 0;
-  __syncthreads();
-  T* mine = tr + wave * P.kseg;
-  for (int at = wave; at < P.n_atiles; at += 4) {
-    const int kl = __builtin_amdgcn_readfirstlane(klo_tab[(size_t)at * P.S + s]);
-    const int lo = max(kl, k0), hi = min(kl + P.wpa, k0 + kn);
-    if (lo >= hi) continue;
-    const T* row = rows + ((size_t)at * P.S + s) * P.wpa;
-    for (int k = lo + lane; k < hi; k += 64) mine[k - k0] += row[k - kl];
-  }
-  __syncthreads();
-  const T scale = sizeof(T) == 4 ? (T)P.out_scale : (T)P.out_scale_d;
+  const int k = k0 + tid;
+  const int* kt = klo_tab + (size_t)s * P.n_atiles;
+  const T* srow = rows + (size_t)s * P.n_atiles * P.wpa;
+  // the part of the segment this wave's lanes cover
+  const int wlo = k0 + wave * 64, whi = min(k0 + kn, wlo + 64);
   double acc = 0.0;
-  T* yrow = y + (size_t)s * P.K + k0;
-  for (int i = tid; i < kn; i += kBlock) {
-    const T v = (((tr[i] + tr[P.kseg + i]) + tr[2 * P.kseg + i]) + tr[3 * P.kseg + i]) * scale;
-    yrow[i] = v;
-    acc += (double)v * (double)v;
+  for (int c0 = 0; c0 < P.n_atiles; c0 += kGatherChunk) {
+    const int nc = min(kGatherChunk, P.n_atiles - c0);
+    // compaction: wave w tests tiles c0 + w * (kGatherChunk / 4) + [0, kGatherChunk / 4)
+    constexpr int PER = kGatherChunk / 4;
+    uint64_t masks[PER / 64];
+    int kls[PER / 64];
+    int n = 0;
+#pragma unroll
+    for (int g = 0; g < PER / 64; ++g) {
+      const int at = wave * PER + g * 64 + lane;
+      int kl = 0;
+      bool ov = false;
+      if (at < nc) {
+        kl = kt[c0 + at];
+        ov = kl < k0 + kn && kl + P.wpa > k0;
+      }
+      masks[g] = __ballot(ov);
+      kls[g] = kl;
+      n += __popcll(masks[g]);
+    }
+    if (lane == 0) wcount[wave] = n;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += wcount[w];
+    const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+#pragma unroll
+    for (int g = 0; g < PER / 64; ++g) {
+      const uint64_t m = masks[g];
+      if ((m >> lane) & 1) {
+        const int pos = base + __popcll(m & ((1ull << lane) - 1));
+        list[pos] = c0 + wave * PER + g * 64 + lane;
+        lkl[pos] = kls[g];
+      }
+      base += __popcll(m);
+    }
+    __syncthreads();
+    // accumulate the listed rows, eight loads in flight at a time
+    for (int i0 = 0; i0 < total; i0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = 0.0;
+        const int i = i0 + u;
+        if (i < total) {
+          const int kl = lkl[i];
+          if (kl < whi && kl + P.wpa > wlo) {  // wave-uniform
+            const int j = k - kl;
+            if (j >= 0 && j < P.wpa && k < k0 + kn) v[u] = (double)srow[(size_t)list[i] * P.wpa + j];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    __syncthreads();  // the list is rebuilt for the next chunk
+  }
+  const double scale = sizeof(T) == 4 ? 2.0 * P.inv_cdt : P.out_scale_d;
+  double q = 0.0;
+  if (tid < kn) {
+    const T out = (T)(acc * scale);
+    y[(size_t)s * P.K + k] = out;
+    q = (double)out * (double)out;
   }
   if (part_q) {
-    acc = block_sum(acc, red);
-    if (tid == 0) part_q[pidx] = acc;
+    q = block_sum(q, red);
+    if (tid == 0) part_q[pidx] = q;
   }
 }
 

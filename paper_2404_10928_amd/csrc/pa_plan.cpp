@@ -5,6 +5,9 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace pa {
 
@@ -28,7 +31,66 @@ int blas_grid(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
 }
 
-pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg) {
+namespace {
+
+struct TuneKey {
+  int32_t ndim, dtype, nx, ny, nz, S, K;
+  uint64_t hs_bits;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(ndim, dtype, nx, ny, nz, S, K, hs_bits) < std::tie(o.ndim, o.dtype, o.nx, o.ny, o.nz, o.S, o.K, o.hs_bits);
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuning>* g_tune = nullptr;
+
+TuneKey tune_key(const pa_geometry* g, pa_dtype dtype) {
+  TuneKey k{g->ndim, (int32_t)dtype, g->nx, g->ny, g->nz, g->n_sensors, g->n_samples, 0};
+  const double hs = g->h / (g->c * g->dt);
+  std::memcpy(&k.hs_bits, &hs, sizeof(hs));
+  return k;
+}
+
+}  // namespace
+
+void tune_store(const pa_geometry* g, pa_dtype dtype, const Tuning& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune) g_tune = new std::map<TuneKey, Tuning>();
+  (*g_tune)[tune_key(g, dtype)] = t;
+}
+
+bool tune_lookup(const pa_geometry* g, pa_dtype dtype, Tuning* t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune) return false;
+  auto it = g_tune->find(tune_key(g, dtype));
+  if (it == g_tune->end()) return false;
+  *t = it->second;
+  return true;
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune) g_tune->clear();
+}
+
+int fwd_tile_candidates(int ndim, int (*out)[3], int max) {
+  static const int c2[][3] = {{1, 1, 1}, {2, 1, 1}, {2, 2, 1}, {4, 2, 1}, {4, 4, 1}};
+  static const int c3[][3] = {{1, 1, 1}, {2, 1, 2}, {2, 2, 2}, {2, 2, 4}, {4, 2, 4}};
+  const int (*c)[3] = ndim == 2 ? c2 : c3;
+  const int n = std::min(5, max);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) out[i][a] = c[i][a];
+  return n;
+}
+
+int adj_lds_candidates(size_t* out, int max) {
+  static const size_t c[] = {24 * 1024, 40 * 1024, kLdsPreferred, 96 * 1024};
+  const int n = std::min(4, max);
+  for (int i = 0; i < n; ++i) out[i] = c[i];
+  return n;
+}
+
+pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg, const Tuning* force) {
   if (!g) return fail(msg, PA_ERR_INVALID_ARGUMENT, "geometry pointer is NULL");
   if (!plan) return fail(msg, PA_ERR_INVALID_ARGUMENT, "plan pointer is NULL");
   if (dtype != PA_F32 && dtype != PA_F64) return fail(msg, PA_ERR_INVALID_ARGUMENT, "dtype must be PA_F32 or PA_F64");
@@ -46,6 +108,10 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   if (g->n_sensors > 0 && !g->sensors) return fail(msg, PA_ERR_INVALID_ARGUMENT, "sensors is NULL but n_sensors > 0");
   if (g->sensors && (reinterpret_cast<uintptr_t>(g->sensors) % 8) != 0)
     return fail(msg, PA_ERR_INVALID_ARGUMENT, "sensors must be 8-byte aligned");
+
+  Tuning tuned{{0, 0, 0}, 0};
+  if (force) tuned = *force;
+  else (void)tune_lookup(g, dtype, &tuned);
 
   const int64_t P = (int64_t)g->nx * g->ny * g->nz;
   const int64_t M = (int64_t)g->n_sensors * g->n_samples;
@@ -127,7 +193,8 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     op.wp = (int32_t)std::ceil(diag) + 5;
     const size_t per = sc_bytes + 8 + near_bytes + (size_t)op.wp * elem;
     const size_t slack = 64;  // alignment of the four LDS arrays
-    int64_t sc_max = (int64_t)((40 * 1024 - slack) / per);
+    const size_t budget = tuned.adj_lds > 0 ? std::min<size_t>((size_t)tuned.adj_lds, kLdsMax) : 40 * 1024;
+    int64_t sc_max = budget > slack ? (int64_t)((budget - slack) / per) : 0;
     if (sc_max < 1) sc_max = (int64_t)((kLdsPreferred - slack) / per);
     if (sc_max < 1) sc_max = (int64_t)((kLdsMax - slack) / per);
     if (sc_max < 1) return fail(msg, PA_ERR_UNSUPPORTED, "trace window of one tile does not fit in LDS (h / (c dt) too large)");
@@ -149,7 +216,26 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     int (*cand)[3] = nd == 2 ? cand2 : cand3;
     const int ncand = nd == 2 ? 2 : 4;
     bool ok = false;
+    if (tuned.fwd_tile[0] > 0 && tuned.fwd_tile[1] > 0 && tuned.fwd_tile[2] > 0) {
+      const int* m = tuned.fwd_tile;
+      const bool shape_ok = nd == 3 || m[2] == 1;
+      double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
+      double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
+      if (shape_ok && diag <= 1e6) {
+        int32_t wpa = ((int32_t)std::ceil(diag) + 5) | 1;
+        int nsub = m[0] * m[1] * m[2];
+        size_t lds = fp_layout(wpa, nsub, elem, pix_bytes).total;
+        if (lds <= kLdsMax) {
+          for (int a = 0; a < 3; ++a) op.msub[a] = m[a];
+          op.nsub = nsub;
+          op.wpa = wpa;
+          pl.fp_lds = lds;
+          ok = true;
+        }
+      }
+    }
     for (size_t budget : {kLdsPreferredFwd, kLdsMax}) {
+      if (ok) break;
       for (int ci = 0; ci < ncand && !ok; ++ci) {
         int* m = cand[ci];
         double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
@@ -173,9 +259,9 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     op.n_atiles = op.natile[0] * op.natile[1] * op.natile[2];
     op.n_chunks = ceil_div(g->n_sensors, kSensorsPerFwdBlock);
     // gather of the partial rows: one work-group per (sensor, segment of kseg samples)
-    op.kseg = std::max(1, std::min<int32_t>(g->n_samples, 1024));
+    op.kseg = std::max(1, std::min<int32_t>(g->n_samples, kBlock));
     op.nseg = g->n_samples > 0 ? ceil_div(g->n_samples, op.kseg) : 0;
-    pl.gather_lds = gather_lds(op.kseg, elem);
+    pl.gather_lds = gather_lds();
     const size_t rows = (size_t)op.n_atiles * (size_t)g->n_sensors * (size_t)op.wpa * elem;
     const size_t tab = (size_t)op.n_atiles * (size_t)g->n_sensors * 4;
     pl.part_rows_off = 0;

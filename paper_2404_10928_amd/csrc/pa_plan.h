@@ -58,7 +58,7 @@ struct OpParams {
   int32_t n_atiles;
   int32_t n_chunks;         // forward: sensor chunks of 64
   int32_t wpa;              // forward: LDS histogram stride of one sensor
-  int32_t kseg;             // forward gather: samples per work-group
+  int32_t kseg;             // forward gather: samples per work-group (<= 256, one per lane)
   int32_t nseg;             // forward gather: segments per trace
   double near_r2;           // squared tile-centre distance (sample units) below which a
                             // sensor takes the FP64 delay path in the FP32 kernels
@@ -97,8 +97,9 @@ PA_HD inline FpLayout fp_layout(int wpa, int nsub, size_t elem, size_t pix_bytes
   return L;
 }
 
-// forward gather: one private copy of the trace segment per wave
-PA_HD inline size_t gather_lds(int kseg, size_t elem) { return 4 * (size_t)kseg * elem; }
+// forward gather: tiles listed per pass, and the LDS of that list
+constexpr int kGatherChunk = 1024;
+PA_HD inline size_t gather_lds() { return 2 * kGatherChunk * sizeof(int); }
 
 struct Plan {
   OpParams op;
@@ -112,9 +113,27 @@ struct Plan {
   size_t part_rows_off, klo_tab_off;  // offsets inside that scratch
 };
 
+// Tiling choices an autotuning run can fix for a geometry shape.  Zero
+// fields leave the planner's own choice.
+struct Tuning {
+  int32_t fwd_tile[3];   // forward operator: base tiles per forward tile, per axis
+  int32_t adj_lds;       // adjoint: LDS budget per work-group (bytes) that sets the sensor chunk
+};
+
 // Fills *plan from g.  Returns PA_OK or an error with *msg set.  Never touches
-// the GPU or dereferences g->sensors.
-pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg);
+// the GPU or dereferences g->sensors.  With force == nullptr the planner uses
+// the tuning recorded for g's shape (see tune_store), if any.
+pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg,
+                    const Tuning* force = nullptr);
+
+// Process-wide table of tunings keyed by shape (ndim, dtype, sizes, S, K and
+// the pixel pitch in samples); thread-safe.
+void tune_store(const pa_geometry* g, pa_dtype dtype, const Tuning& t);
+bool tune_lookup(const pa_geometry* g, pa_dtype dtype, Tuning* t);
+void tune_clear();
+// Candidate tilings the autotuner times for a geometry of this ndim.
+int fwd_tile_candidates(int ndim, int (*out)[3], int max);
+int adj_lds_candidates(size_t* out, int max);
 
 // One frame of a batch as the batched kernels see it (device table, sorted
 // by work, largest first).  Block ranges [b_*, b_* + n_*) are those of each

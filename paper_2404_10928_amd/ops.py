@@ -353,3 +353,23 @@ class Batch:
         _lib.check(self._lib.pa_batch_stop_iterations(self._h, self._ws_cg[iters].data_ptr(), iters, out),
                    allow=(_lib.PA_OK, _lib.PA_ERR_BREAKDOWN))
         return [int(v) for v in out]
+
+
+def autotune(geom, dtype: torch.dtype = torch.float32, device=None) -> dict:
+    """Times the candidate tilings of A and A^T on this geometry and records the
+    fastest for every later plan of the same shape (process-wide).  Returns the
+    choice and its measured times."""
+    g = as_device_geometry(geom, device)
+    x = torch.zeros(g.image_shape, dtype=dtype, device=g.device)
+    y = torch.zeros(g.data_shape, dtype=dtype, device=g.device)
+    t = _lib.PaTuning()
+    lib = _lib.load()
+    _lib.check(lib.pa_autotune(ctypes.byref(g.c_struct()), _code(x), x.data_ptr() or None, y.data_ptr() or None,
+                               _stream(g.device), ctypes.byref(t)))
+    return {"fwd_tile": tuple(int(v) for v in t.fwd_tile), "adj_lds_bytes": int(t.adj_lds_bytes),
+            "fwd_us": float(t.fwd_us), "adj_us": float(t.adj_us)}
+
+
+def tuning_clear() -> None:
+    """Forgets every recorded tiling."""
+    _lib.check(_lib.load().pa_tuning_clear())

@@ -175,3 +175,14 @@ def test_batch_rejects_bad_frames_on_host(lib):
     frames[1].sensors = 4096 * 3
     assert lib.pa_batch_create(frames, 2, 0, ctypes.byref(h)) == 1
     assert b"ndim" in lib.pa_last_error()
+
+
+def test_autotune_argument_checks_on_host(lib):
+    vp = ctypes.c_void_p
+    lib.pa_autotune.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, vp, vp, vp, vp]
+    g = good()
+    assert lib.pa_autotune(ctypes.byref(g), 0, None, 1 << 20, None, None) == 1
+    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, (1 << 20) + 64, None, None) == 1
+    g.dt = -1.0
+    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, 1 << 28, None, None) == 1
+    assert lib.pa_tuning_clear() == 0
