@@ -54,6 +54,8 @@ def _configure(lib):
                                 ctypes.c_int]
         lib.or_landweber.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      dp, ctypes.c_int]
+        lib.or_power_sigma2.argtypes = [gp, ctypes.c_int, ctypes.c_int]
+        lib.or_power_sigma2.restype = ctypes.c_double
         lib.or_tv2d.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, dp]
         lib.or_tv2d.restype = ctypes.c_double
     return lib
@@ -152,6 +154,17 @@ def landweber(g, y, iters, lam, omega, threads=None):
                         _dp(hist), _threads(threads)) != 0:
         raise ValueError("oracle: bad arguments")
     return x, hist
+
+
+def power_sigma2(g, iters=30, threads=None):
+    """Largest eigenvalue of A^T A after `iters` power-iteration steps from the
+    all-ones vector (the gradient iteration's step-size estimate)."""
+    lib = _load()
+    cg, keep = _geom(g)
+    v = lib.or_power_sigma2(ctypes.byref(cg), int(iters), _threads(threads))
+    if v < 0:
+        raise ValueError("oracle: bad arguments")
+    return float(v)
 
 
 def tv2d(x, eps=1e-8):

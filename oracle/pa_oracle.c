@@ -221,6 +221,32 @@ int or_landweber(const or_geom* g, const double* y, double* x, int iters, double
   return 0;
 }
 
+/* Largest eigenvalue of A^T A by power iteration (the step-size estimate of
+ * the gradient iteration): v_0 = (1, ..., 1) / sqrt(P); for each of `iters`
+ * steps w = A^T A v, sigma2 = ||w||, v = w / ||w||.  Returns sigma2 after the
+ * last step, 0 when A^T A v vanishes, or -1 on bad arguments. */
+double or_power_sigma2(const or_geom* g, int iters, int threads) {
+  if (!geom_ok(g) || iters < 1) return -1.0;
+  const int64_t P = npix(g);
+  const int64_t M = (int64_t)g->n_sensors * g->n_samples;
+  if (P == 0 || M == 0) return 0.0;
+  double* v = (double*)malloc(sizeof(double) * P);
+  double* w = (double*)malloc(sizeof(double) * P);
+  double* q = (double*)malloc(sizeof(double) * M);
+  if (!v || !w || !q) { free(v); free(w); free(q); return -1.0; }
+  for (int64_t i = 0; i < P; ++i) v[i] = 1.0 / sqrt((double)P);
+  double sigma2 = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    or_forward(g, v, q, threads);
+    or_adjoint(g, q, w, threads);
+    sigma2 = sqrt(dot(w, w, P));
+    if (!(sigma2 > 0.0)) { sigma2 = 0.0; break; }
+    for (int64_t i = 0; i < P; ++i) v[i] = w[i] / sigma2;
+  }
+  free(v); free(w); free(q);
+  return sigma2;
+}
+
 /* TV_eps(x) = sum_p m_p, m_p = sqrt(dx_p^2 + dy_p^2 + eps^2),
  * dx_p = x[iy][ix+1] - x[iy][ix] (0 in the last column), dy_p likewise.
  * dTV/dx[q] collects, from every m_p whose differences contain x[q],

@@ -53,6 +53,9 @@ int or_cgls(const or_geom* g, const double* y, double* x, int iters, double lamb
  * hist (may be NULL): [iters+1] = F_k. Returns 0 / -1. */
 int or_landweber(const or_geom* g, const double* y, double* x, int iters, double lambda,
                  double omega, double* hist, int threads);
+/* Largest eigenvalue of A^T A by `iters` power-iteration steps from the
+ * all-ones vector (see the source). */
+double or_power_sigma2(const or_geom* g, int iters, int threads);
 
 /* Isotropic smoothed total variation of one 2D image [ny][nx] (the TV term of
  * the paper's objective, Eq. 8): TV = sum_p sqrt(dx_p^2 + dy_p^2 + eps^2) with

@@ -276,6 +276,21 @@ def test_landweber_closed_form():
     assert np.all(np.diff(hist) <= 1e-12 * hist[0])
 
 
+def test_power_iteration_reaches_the_largest_singular_value():
+    """sigma2 from power iteration on A^T A equals ||A||_2^2 of the dense
+    matrix (numpy SVD) once converged, and never exceeds it."""
+    g, _ = tiny_problem(4)
+    A = dense(g)
+    smax2 = np.linalg.norm(A, 2) ** 2
+    s200 = oracle.power_sigma2(g, 200)
+    s3 = oracle.power_sigma2(g, 3)
+    assert abs(s200 / smax2 - 1) <= 1e-8
+    assert s3 <= smax2 * (1 + 1e-12) and s3 >= 0.5 * smax2
+    # one step from the all-ones vector: ||A^T A 1|| / sqrt(P)
+    one = np.ones(A.shape[1]) / np.sqrt(A.shape[1])
+    assert abs(oracle.power_sigma2(g, 1) / np.linalg.norm(A.T @ (A @ one)) - 1) <= 1e-12
+
+
 # --------------------------------------------------------------------------
 # total variation term (Eq. 8) and the loss gradient
 
