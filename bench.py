@@ -226,6 +226,7 @@ def main():
     if not args.quick and not args.no_extras:
         out["batched_frames"] = batched_leg(pa, torch, dev)
         out["volume_3d"] = volume_leg(pa, torch, dev)
+        out["landweber"] = landweber_leg(pa, torch, dev, geom, y, w)
 
     print(json.dumps(out))
     return 0
@@ -274,6 +275,19 @@ def batched_leg(pa, torch, dev):
             "frame_iterations_per_s_batched": n * w.iters / t_b,
             "frame_iterations_per_s_single_frame_loop": n * w.iters / t_s,
             "speedup": t_s / t_b, "max_rel_l2_batched_vs_single": max(diffs)}
+
+
+def landweber_leg(pa, torch, dev, geom, y, w):
+    """The gradient iteration on the 512x512 workload: 50 steps with the step
+    size from 30 power-iteration steps, FP32, one graph replay per solve."""
+    sv = pa.LandweberSolver(geom, torch.float32, w.iters, w.lam, omega=0.0, power_iters=30, graph=True, device=dev)
+    x = torch.empty(geom.image_shape, dtype=torch.float32, device=dev)
+    sv.solve(y, x)
+    t = _sync_time(torch, lambda: sv.solve(y, x), 3)
+    om, s2 = sv.step()
+    return {"workload": f"512x512 ring workload, {w.iters} Landweber steps + 30 power-iteration steps, FP32",
+            "ms_per_solve": t * 1e3, "solves_per_s": 1.0 / t, "sigma2": s2, "omega": om,
+            "F_first": float(sv.history[0]), "F_last": float(sv.history[-1])}
 
 
 def volume_leg(pa, torch, dev):

@@ -121,6 +121,28 @@ pa_status pa_cgls_solve(const pa_geometry* g, pa_dtype dtype, const void* y, voi
  * device-to-host copy. */
 pa_status pa_cgls_stop_iteration(const void* workspace, int32_t* stop_iter);
 
+/* ------------------------------------------------------- gradient iteration
+ * Landweber iteration on the same objective (the gradient loop of Experiment
+ * 2 / Table 3, whose statement t1 = 2 K^T (K x - y) is the gradient of the
+ * data term):
+ *   x_{k+1} = x_k + omega (A^T (y - A x_k) - lambda x_k),   k = 0 .. iters-1
+ * With omega > 0 the caller's step is used.  With omega == 0 the step is
+ * omega = 1 / (sigma2 + lambda), where sigma2 estimates the largest
+ * eigenvalue of A^T A by power_iters power-iteration steps from the all-ones
+ * vector (v <- A^T A v / ||A^T A v||; sigma2 = ||A^T A v|| at the last step),
+ * all on the GPU.
+ * history: device double [iters + 1], F_k = ||y - A x_k||^2 + lambda ||x_k||^2
+ * for k = 0 .. iters, or NULL.  Flags, workspace rules and errors as for
+ * pa_cgls_solve; PA_X0_ZERO starts from 0. */
+size_t pa_landweber_workspace_bytes(const pa_geometry* g, pa_dtype dtype);
+pa_status pa_landweber_solve(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, int32_t iters,
+                             double lambda, double omega, int32_t power_iters, uint32_t flags, void* workspace,
+                             size_t workspace_bytes, double* history, void* hip_stream);
+
+/* After synchronising: the step the last solve on this workspace used, and
+ * the eigenvalue estimate (0 when the step was given).  One blocking copy. */
+pa_status pa_landweber_step(const void* workspace, double* omega, double* sigma2);
+
 /* ------------------------------------------------------------------ batches
  * Many frames of uneven image size, sensor count and trace length, each with
  * its own geometry, processed by one launch per step.  Frame i's image and

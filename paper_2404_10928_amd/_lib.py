@@ -31,7 +31,8 @@ PA_USE_GRAPH = 2
 EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspace_bytes", "pa_cgls_solve",
            "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version", "pa_batch_create", "pa_batch_destroy",
            "pa_batch_offsets", "pa_batch_workspace_bytes", "pa_batch_cgls_workspace_bytes", "pa_batch_forward",
-           "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations", "pa_autotune", "pa_tuning_clear"]
+           "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations", "pa_autotune", "pa_tuning_clear",
+           "pa_landweber_workspace_bytes", "pa_landweber_solve", "pa_landweber_step"]
 
 
 class PaTuning(ctypes.Structure):
@@ -104,6 +105,14 @@ def load(path: str = LIB_PATH):
     lib.pa_autotune.restype = ctypes.c_int
     lib.pa_tuning_clear.argtypes = []
     lib.pa_tuning_clear.restype = ctypes.c_int
+    lib.pa_landweber_workspace_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_landweber_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_landweber_solve.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_uint32, vp, ctypes.c_size_t, vp, vp]
+    lib.pa_landweber_solve.restype = ctypes.c_int
+    dpp = ctypes.POINTER(ctypes.c_double)
+    lib.pa_landweber_step.argtypes = [vp, dpp, dpp]
+    lib.pa_landweber_step.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -131,6 +131,78 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
   return hipSuccess;
 }
 
+// ------------------------------------------------------- Landweber enqueue
+
+struct LwSolve {
+  const pa::Plan* pl;
+  pa::LwLayout L;
+  const void* y;
+  void* x;
+  int iters;
+  double lambda;
+  double omega;      // > 0: given; 0: estimated by power iteration
+  int power_iters;
+  uint32_t flags;
+  unsigned char* ws;
+  double* hist;
+};
+
+hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
+  const pa::Plan& pl = *S.pl;
+  const pa::LwLayout& L = S.L;
+  const pa_dtype dt = pl.dtype;
+  unsigned char* ws = S.ws;
+  int* status = reinterpret_cast<int*>(ws + L.status);
+  double* alpha0 = reinterpret_cast<double*>(ws + L.alpha0);
+  double* sigma2 = reinterpret_cast<double*>(ws + L.sigma2);
+  double* omega = reinterpret_cast<double*>(ws + L.omega);
+  double* part_r = reinterpret_cast<double*>(ws + L.part_r);
+  double* part_s = reinterpret_cast<double*>(ws + L.part_s);
+  double* part_x = reinterpret_cast<double*>(ws + L.part_x);
+  double* part_n = reinterpret_cast<double*>(ws + L.part_n);
+  void* r = ws + L.vec_r;
+  void* q = ws + L.vec_q;
+  void* s = ws + L.vec_s;
+  void* v = ws + L.vec_v;
+  void* fwd = ws + L.fwd;
+  hipError_t e;
+  // step size
+  if ((e = pa::launch_fill(PA_F64, sigma2, 1, st)) != hipSuccess) return e;
+  if (!(S.omega > 0.0) && pl.P > 0) {
+    if ((e = pa::launch_fill_value(dt, v, pl.P, 1.0 / std::sqrt((double)pl.P), st)) != hipSuccess) return e;
+    for (int it = 0; it < S.power_iters; ++it) {
+      if ((e = pa::launch_forward(pl, v, q, fwd, nullptr, st)) != hipSuccess) return e;
+      if (pl.bp_grid > 0 && (e = pa::launch_adjoint(pl, q, s, nullptr, st)) != hipSuccess) return e;
+      if ((e = pa::launch_norm2(dt, s, pl.P, part_n, st)) != hipSuccess) return e;
+      if ((e = pa::launch_pw_scale(dt, v, s, pl.P, part_n, sigma2, st)) != hipSuccess) return e;
+    }
+  }
+  if ((e = pa::launch_pw_omega(sigma2, S.lambda, S.omega, omega, st)) != hipSuccess) return e;
+  if (S.flags & PA_X0_ZERO)
+    if ((e = pa::launch_fill(dt, S.x, pl.P, st)) != hipSuccess) return e;
+  const int gbp = std::max(pl.bp_grid, 1);
+  // s = A^T r - lambda x with x unchanged (the epilogue's step is the zero that init_r writes)
+  pa::CgArgs cg{S.x, S.x, alpha0, S.lambda, part_s, part_x};
+  for (int k = 0; k < S.iters; ++k) {
+    if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
+    if (pl.bp_grid == 0) {
+      if ((e = pa::launch_fill(PA_F64, part_s, gbp, st)) != hipSuccess) return e;
+      if ((e = pa::launch_fill(PA_F64, part_x, gbp, st)) != hipSuccess) return e;
+    } else if ((e = pa::launch_adjoint(pl, r, s, &cg, st)) != hipSuccess) {
+      return e;
+    }
+    if ((e = pa::launch_lw_step(dt, S.x, s, pl.P, part_r, L.g_m, part_x, gbp, S.lambda, omega, S.hist, k, st)) !=
+        hipSuccess)
+      return e;
+  }
+  // F at the final iterate
+  if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
+  if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
+  if ((e = pa::launch_norm2(dt, S.x, pl.P, part_n, st)) != hipSuccess) return e;
+  return pa::launch_lw_final(part_r, L.g_m, part_n, L.g_p, S.lambda, S.hist, S.iters, st);
+}
+
 // ------------------------------------------------------------ graph cache
 
 struct GraphKey {
@@ -145,6 +217,9 @@ struct GraphKey {
   void* ws;
   double* hist;
   int device;
+  int kind;           // 0 CGLS, 1 Landweber
+  double omega;       // Landweber: given step (0: estimated)
+  int power_iters;    // Landweber: power-iteration steps
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
@@ -733,6 +808,86 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
 pa_status pa_tuning_clear(void) {
   g_err.clear();
   pa::tune_clear();
+  return PA_OK;
+}
+
+size_t pa_landweber_workspace_bytes(const pa_geometry* g, pa_dtype dtype) {
+  g_err.clear();
+  pa::Plan pl;
+  if (plan_or_fail(g, dtype, &pl) != PA_OK) return 0;
+  return pa::lw_layout(pl).total;
+}
+
+pa_status pa_landweber_solve(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, int32_t iters,
+                             double lambda, double omega, int32_t power_iters, uint32_t flags, void* workspace,
+                             size_t workspace_bytes, double* history, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = plan_or_fail(g, dtype, &pl);
+  if (st != PA_OK) return st;
+  if (iters < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+  if (iters > (1 << 20) || power_iters > (1 << 20)) return set_err(PA_ERR_UNSUPPORTED, "iteration count above 2^20");
+  if (!std::isfinite(lambda) || lambda < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "lambda must be finite and >= 0");
+  if (!std::isfinite(omega) || omega < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "omega must be finite and >= 0");
+  if (omega == 0.0 && power_iters < 1)
+    return set_err(PA_ERR_INVALID_ARGUMENT, "omega == 0 needs power_iters >= 1 to estimate the step");
+  if (flags & ~(PA_X0_ZERO | PA_USE_GRAPH)) return set_err(PA_ERR_INVALID_ARGUMENT, "unknown flag bits");
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if (history && !aligned(history, 8)) return set_err(PA_ERR_INVALID_ARGUMENT, "history is not 8-byte aligned");
+  const pa::LwLayout L = pa::lw_layout(pl);
+  if (!workspace) return set_err(PA_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (workspace_bytes < L.total) return set_err(PA_ERR_WORKSPACE, "workspace smaller than pa_landweber_workspace_bytes()");
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  if (overlap(workspace, L.total, x, pl.P * pl.elem) || overlap(workspace, L.total, y, pl.M * pl.elem))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "workspace overlaps x or y");
+  const size_t hb = sizeof(double) * (size_t)(iters + 1);
+  if (history && (overlap(history, hb, workspace, L.total) || overlap(history, hb, x, pl.P * pl.elem) ||
+                  overlap(history, hb, y, pl.M * pl.elem)))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "history overlaps another buffer");
+  LwSolve S{&pl, L, y, x, iters, lambda, omega, omega > 0.0 ? 0 : power_iters, flags,
+            static_cast<unsigned char*>(workspace), history};
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  bool use_graph = (flags & PA_USE_GRAPH) != 0;
+  if (use_graph && s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    PA_HIP(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) use_graph = false;
+  }
+  if (!use_graph) {
+    PA_HIP(enqueue_landweber(S, s), "Landweber enqueue");
+    return PA_OK;
+  }
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.g = *g;
+  key.dt = dtype;
+  key.y = y;
+  key.x = x;
+  key.iters = iters;
+  key.lambda = lambda;
+  key.flags = flags;
+  key.ws = workspace;
+  key.hist = history;
+  key.kind = 1;
+  key.omega = omega;
+  key.power_iters = S.power_iters;
+  PA_HIP(hipGetDevice(&key.device), "hipGetDevice");
+  hipGraphExec_t exec = nullptr;
+  PA_HIP(get_graph(key, [&](hipStream_t cs) { return enqueue_landweber(S, cs); }, &exec), "Landweber graph capture");
+  PA_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
+  return PA_OK;
+}
+
+pa_status pa_landweber_step(const void* workspace, double* omega, double* sigma2) {
+  g_err.clear();
+  if (!workspace) return set_err(PA_ERR_INVALID_ARGUMENT, "workspace is NULL");
+  double v[3] = {0, 0, 0};  // sigma2, omega follow alpha0 in the layout
+  PA_HIP(hipMemcpy(v, static_cast<const unsigned char*>(workspace) + 64, sizeof(v), hipMemcpyDeviceToHost),
+         "read Landweber step");
+  if (sigma2) *sigma2 = v[1];
+  if (omega) *omega = v[2];
   return PA_OK;
 }
 

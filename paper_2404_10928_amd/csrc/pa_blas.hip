@@ -291,4 +291,123 @@ hipError_t launch_dir_batched(const BatchLaunch& L, void* p, const void* s, cons
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ gradient iteration
+// Landweber steps and the power iteration that estimates their step size.
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fill_value_kernel(T* __restrict__ p, int64_t n, double v) {
+  const T t = (T)v;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = t;
+}
+
+// partial sums of ||v||^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) norm2_kernel(const T* __restrict__ v, int64_t n, double* __restrict__ part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const double t = (double)v[i];
+    acc += t * t;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// sigma2 = ||w|| (w = A^T A v with ||v|| = 1), v = w / sigma2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) pw_scale_kernel(T* __restrict__ v, const T* __restrict__ w, int64_t n,
+                                                          const double* __restrict__ part, int gp,
+                                                          double* __restrict__ sigma2) {
+  __shared__ double red[4];
+  const double nw = sqrt(sum_partials(part, gp, red));
+  const double inv = nw > 0.0 ? 1.0 / nw : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    v[i] = (T)((double)w[i] * inv);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *sigma2 = nw;
+}
+
+// omega = 1 / (sigma2 + lambda), or the caller's omega when it is > 0.
+__global__ void pw_omega_kernel(const double* __restrict__ sigma2, double lambda, double given,
+                                double* __restrict__ omega) {
+  if (threadIdx.x == 0) {
+    const double d = *sigma2 + lambda;
+    *omega = given > 0.0 ? given : (d > 0.0 ? 1.0 / d : 0.0);
+  }
+}
+
+// hist[k] = ||r_k||^2 + lambda ||x_k||^2 from the partials; then x += omega s.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lw_step_kernel(T* __restrict__ x, const T* __restrict__ s, int64_t np,
+                                                         const double* __restrict__ part_r, int gr,
+                                                         const double* __restrict__ part_x, int gx, double lambda,
+                                                         const double* __restrict__ omega, double* __restrict__ hist,
+                                                         int k) {
+  __shared__ double red[4];
+  const double rr = sum_partials(part_r, gr, red);
+  const double xx = sum_partials(part_x, gx, red);
+  const double w = *omega;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < np; i += (int64_t)gridDim.x * kBlock)
+    x[i] = (T)((double)x[i] + w * (double)s[i]);
+  if (hist && blockIdx.x == 0 && threadIdx.x == 0) hist[k] = rr + lambda * xx;
+}
+
+__global__ void lw_final_kernel(const double* __restrict__ part_r, int gr, const double* __restrict__ part_x, int gx,
+                                double lambda, double* __restrict__ hist, int k) {
+  __shared__ double red[4];
+  const double rr = sum_partials(part_r, gr, red);
+  const double xx = sum_partials(part_x, gx, red);
+  if (hist && threadIdx.x == 0) hist[k] = rr + lambda * xx;
+}
+
+hipError_t launch_fill_value(pa_dtype dt, void* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int g = blas_grid(n);
+  if (dt == PA_F32) fill_value_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(p), n, v);
+  else fill_value_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(p), n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(pa_dtype dt, const void* v, int64_t n, double* part, hipStream_t st) {
+  const int g = blas_grid(n);
+  if (dt == PA_F32) norm2_kernel<float><<<g, kBlock, 0, st>>>(static_cast<const float*>(v), n, part);
+  else norm2_kernel<double><<<g, kBlock, 0, st>>>(static_cast<const double*>(v), n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_pw_scale(pa_dtype dt, void* v, const void* w, int64_t n, const double* part, double* sigma2,
+                           hipStream_t st) {
+  const int g = blas_grid(n);
+  if (dt == PA_F32)
+    pw_scale_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(v), static_cast<const float*>(w), n, part, g,
+                                                 sigma2);
+  else
+    pw_scale_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(v), static_cast<const double*>(w), n, part, g,
+                                                  sigma2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pw_omega(const double* sigma2, double lambda, double given, double* omega, hipStream_t st) {
+  pw_omega_kernel<<<1, 64, 0, st>>>(sigma2, lambda, given, omega);
+  return hipGetLastError();
+}
+
+hipError_t launch_lw_step(pa_dtype dt, void* x, const void* s, int64_t np, const double* part_r, int gr,
+                          const double* part_x, int gx, double lambda, const double* omega, double* hist, int k,
+                          hipStream_t st) {
+  const int g = blas_grid(np);
+  if (dt == PA_F32)
+    lw_step_kernel<float><<<g, kBlock, 0, st>>>(static_cast<float*>(x), static_cast<const float*>(s), np, part_r, gr,
+                                                part_x, gx, lambda, omega, hist, k);
+  else
+    lw_step_kernel<double><<<g, kBlock, 0, st>>>(static_cast<double*>(x), static_cast<const double*>(s), np, part_r,
+                                                 gr, part_x, gx, lambda, omega, hist, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_lw_final(const double* part_r, int gr, const double* part_x, int gx, double lambda, double* hist,
+                           int k, hipStream_t st) {
+  lw_final_kernel<<<1, kBlock, 0, st>>>(part_r, gr, part_x, gx, lambda, hist, k);
+  return hipGetLastError();
+}
+
 }  // namespace pa

@@ -33,6 +33,18 @@ hipError_t launch_dir(pa_dtype dt, void* p, const void* s, int64_t np, void* q, 
                       const double* part_x, int gx, const double* part_r, int gr, double lambda, double* gamma, int k,
                       const int* status, double* hist, double* part_p, hipStream_t st);
 
+// Gradient (Landweber) iteration and its power-iteration step size.
+hipError_t launch_fill_value(pa_dtype dt, void* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_norm2(pa_dtype dt, const void* v, int64_t n, double* part, hipStream_t st);  // blas_grid(n) partials
+hipError_t launch_pw_scale(pa_dtype dt, void* v, const void* w, int64_t n, const double* part, double* sigma2,
+                           hipStream_t st);
+hipError_t launch_pw_omega(const double* sigma2, double lambda, double given, double* omega, hipStream_t st);
+hipError_t launch_lw_step(pa_dtype dt, void* x, const void* s, int64_t np, const double* part_r, int gr,
+                          const double* part_x, int gx, double lambda, const double* omega, double* hist, int k,
+                          hipStream_t st);
+hipError_t launch_lw_final(const double* part_r, int gr, const double* part_x, int gx, double lambda, double* hist,
+                           int k, hipStream_t st);
+
 // ------------------------------------------------------------------ batches
 
 // Index of the frame whose block range of one batched launch contains global

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pa_device.h"
 #include "pa_plan.h"
 
@@ -473,13 +475,20 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
   constexpr bool F32 = sizeof(T) == 4;
   extern __shared__ __align__(16) unsigned char smem[];
   const FpLayout L = fp_layout(P.wpa, P.nsub, sizeof(T), sizeof(PX));
-  // The histogram accumulates in FP64 in both precisions: FP64 LDS adds are
-  // fast on gfx950 (and FP32 LDS float adds are not), and they sum exactly
-  // enough that the rows round to FP32 only once, when they are written out.
-  double* hist = reinterpret_cast<double*>(smem + L.hist);
+  // Histogram bins.  FP64 kernels add doubles.  FP32 kernels add 32-bit
+  // fixed-point integers (LDS float adds are slow on gfx950, integer adds are
+  // not): lane s scales its taps by 2^30 / B_s, where B_s bounds the sum of
+  // |tap| over the whole forward tile, so no bin can overflow; integer sums
+  // do not depend on their order, and each row is converted back once, when
+  // it is written out.
+  using H = typename std::conditional<F32, int, double>::type;
+  constexpr int HB = (int)sizeof(H);
+  H* hist = reinterpret_cast<H*>(smem + L.hist);
   PX* pixtab = reinterpret_cast<PX*>(smem + L.pixtab);
   T* xs = reinterpret_cast<T*>(smem + L.xs);
   int* klo_a = reinterpret_cast<int*>(smem + L.klo);
+  double* inv_a = reinterpret_cast<double*>(smem + L.inv);
+  __shared__ double red[4];
 
   const int chunk = b % P.n_chunks;
   const int at = b / P.n_chunks;
@@ -525,6 +534,44 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
     kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wpa);
   }
   const bool active = s_ok && in_trace;
+  // Fixed-point scale: a tap of pixel p in base tile m is at most
+  // |x_p| / (2 dmin_m), dmin_m being the distance from this lane's sensor to
+  // base tile m (clamped at r_min), so B_s = sum_m (sum_{p in m} |x_p|) /
+  // (2 dmin_m) bounds every partial sum of the row.
+  float scl = 0.f;
+  if constexpr (F32) {
+    double* sa_m = reinterpret_cast<double*>(smem + L.inv) + NS;  // [nsub][4] per-wave partials
+    for (int m = 0; m < P.nsub; ++m) {
+      double v = fabs((double)xs[m * kBlock + tid]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) sa_m[m * 4 + wave] = v;
+    }
+    __syncthreads();
+    double bound = 0.0;
+    for (int m = 0; m < P.nsub; ++m) {
+      const double sa = (sa_m[m * 4 + 0] + sa_m[m * 4 + 1]) + (sa_m[m * 4 + 2] + sa_m[m * 4 + 3]);
+      if (sa == 0.0) continue;
+      const int bx = ax * P.msub[0] + m % P.msub[0];
+      const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
+      const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
+      double r0[3], lo[3], hi[3];
+      tile_ref<ND>(P, bx, by, bz, r0);
+      const int T3[3] = {TX, TY, TZ};
+      double d2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < ND; ++a) {
+        lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
+        hi[a] = r0[a] + 0.5 * (T3[a] - 1) * P.hs;
+        const double e = fmax(fmax(lo[a] - sp[a], sp[a] - hi[a]), 0.0);
+        d2 += e * e;
+      }
+      bound += sa * (0.5 / fmax(sqrt(d2), P.rmin));
+    }
+    bound *= 1.0 + 1.0 / 1024.0;
+    if (bound > 0.0 && bound < 1e300) scl = (float)(1073741824.0 / bound);
+    if (wave == 0) inv_a[lane] = scl > 0.f ? 1.0 / (double)scl : 0.0;
+  }
   if (wave == 0) klo_a[lane] = active ? kl : P.K + 8;
   for (int e = tid; e < NS * P.wpa; e += kBlock) hist[e] = 0;
   __syncthreads();
@@ -545,9 +592,9 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
     // the wave never runs the FP64 delay path for all of its pixels.
     const bool near = F32 && active && is_near(P, ref, sp);
     SC c;
-    make_sc<ND>(P, ref, sp, kl, lane * P.wpa, 8, active && !near, c);
+    make_sc<ND>(P, ref, sp, kl, lane * P.wpa, HB, active && !near, c);
     c.BASE += (int)(size_t)hist;  // absolute LDS byte address
-    asm volatile("" : "+v"(c.BASE));  // keep "k * 8 + BASE" a single shift-add
+    asm volatile("" : "+v"(c.BASE));  // keep "k * HB + BASE" a single shift-add
     const T* xm = xs + m * kBlock;
     // Every pixel of the base tile, in order.  Pixels beyond the image edge
     // have x = 0 (and taps inside the window), so they add zeros.  The next
@@ -565,13 +612,20 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
       xn = xm[pq];
       int kb;
       T f, wt;
-      phase<ND, FRAC, 8>(c, px, t0f, kb, f, wt);
-      const double v = (double)(wt * xp);
-      const double a1 = v * (double)f;
-      const double a0 = v - a1;
-      double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
-      lds_add(bin, a0);
-      lds_add(bin + 1, a1);
+      phase<ND, FRAC, HB>(c, px, t0f, kb, f, wt);
+      H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
+      if constexpr (F32) {
+        const float vs = (wt * xp) * scl;
+        const int it = (int)__builtin_rintf(vs);
+        const int i1 = (int)__builtin_rintf(vs * f);
+        lds_add(bin, it - i1);
+        lds_add(bin + 1, i1);
+      } else {
+        const double v = wt * xp;
+        const double a1 = v * f;
+        lds_add(bin, v - a1);
+        lds_add(bin + 1, a1);
+      }
     }
     if constexpr (F32) {
       uint64_t nm = __ballot(near);
@@ -580,7 +634,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
         // this lane's row base for its own sensor, as the far constants would have it
         const double kr_l = rint(sqrt((ref[0] - sp[0]) * (ref[0] - sp[0]) + (ref[1] - sp[1]) * (ref[1] - sp[1]) +
                                       (ref[2] - sp[2]) * (ref[2] - sp[2])));
-        const int base_l = ((int)kr_l - P.t0i - kl + lane * P.wpa) * 8 + (int)(size_t)hist;
+        const int base_l = ((int)kr_l - P.t0i - kl + lane * P.wpa) * HB + (int)(size_t)hist;
         while (nm != 0) {
           const int j = __builtin_ctzll(nm);
           nm &= nm - 1;
@@ -590,6 +644,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
           nn.DZ = ref[2] - __shfl(sp[2], j);
           nn.KR = __shfl(kr_l, j);
           const int base = __shfl(base_l, j);
+          const float scl_j = __shfl(scl, j);
           for (int pix = lane; pix < TX * TY * TZ; pix += 64) {
             const int lx = pix % TX, ly = (pix / TX) % TY, lz = pix / (TX * TY);
             if (lx >= nlx || ly >= nly || lz >= nlz) continue;
@@ -597,13 +652,13 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
             pix_offsets<ND>(P, lx, ly, lz, o);
             int kb;
             float f, wt;
-            phase_near<ND, FRAC, 8>(nn, o, rmin2, P.t0fd, base, 0.5f, kb, f, wt);
-            const double v = (double)(wt * xm[pix]);
-            const double a1 = v * (double)f;
-            const double a0 = v - a1;
-            double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
-            lds_add(bin, a0);
-            lds_add(bin + 1, a1);
+            phase_near<ND, FRAC, HB>(nn, o, rmin2, P.t0fd, base, 0.5f, kb, f, wt);
+            const float vs = (wt * xm[pix]) * scl_j;
+            const int it = (int)__builtin_rintf(vs);
+            const int i1 = (int)__builtin_rintf(vs * f);
+            H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
+            lds_add(bin, it - i1);
+            lds_add(bin + 1, i1);
           }
         }
       }
@@ -616,7 +671,12 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
     const int sj = chunk * NS + j;
     if (sj >= P.S) break;
     T* row = rows + ((size_t)sj * P.n_atiles + at) * P.wpa;
-    for (int i = lane; i < P.wpa; i += 64) row[i] = (T)hist[j * P.wpa + i];
+    if constexpr (F32) {
+      const double inv = inv_a[j];
+      for (int i = lane; i < P.wpa; i += 64) row[i] = (T)((double)hist[j * P.wpa + i] * inv);
+    } else {
+      for (int i = lane; i < P.wpa; i += 64) row[i] = (T)hist[j * P.wpa + i];
+    }
   }
   if (wave == 0 && s_ok) klo_tab[(size_t)s * P.n_atiles + at] = klo_a[lane];
 }

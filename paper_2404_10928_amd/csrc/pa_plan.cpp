@@ -307,6 +307,30 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   return L;
 }
 
+LwLayout lw_layout(const Plan& plan) {
+  LwLayout L{};
+  const size_t A = 256;
+  L.g_m = blas_grid(plan.M);
+  L.g_p = blas_grid(plan.P);
+  L.g_bp = std::max(plan.op.n_tiles, 1);
+  size_t off = 0;
+  L.status = off; off += 64;
+  L.alpha0 = off; off += 8;
+  L.sigma2 = off; off += 8;
+  L.omega = off; off = align_up(off + 8, A);
+  L.part_r = off; off = align_up(off + sizeof(double) * L.g_m, A);
+  L.part_s = off; off = align_up(off + sizeof(double) * L.g_bp, A);
+  L.part_x = off; off = align_up(off + sizeof(double) * L.g_bp, A);
+  L.part_n = off; off = align_up(off + sizeof(double) * L.g_p, A);
+  L.vec_r = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
+  L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
+  L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.vec_v = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.fwd = off; off = align_up(off + std::max<size_t>(plan.fwd_scratch, 256), A);
+  L.total = off;
+  return L;
+}
+
 pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, BatchPlan* bp,
                           std::string* msg) {
   if (!bp) return fail(msg, PA_ERR_INVALID_ARGUMENT, "batch plan pointer is NULL");

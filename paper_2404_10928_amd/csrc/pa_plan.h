@@ -84,16 +84,20 @@ PA_HD inline BpLayout bp_layout(int sc, int wp, size_t elem, size_t sc_bytes, si
 }
 
 struct FpLayout {
-  size_t hist, pixtab, xs, klo, total;
+  size_t hist, pixtab, xs, klo, inv, total;
 };
-// The forward histogram is FP64 in both precisions (elem is the x element size).
+// Histogram bins have the element size elem: 32-bit fixed point for FP32,
+// double for FP64.  inv: per-sensor inverse fixed-point scale and the
+// per-base-tile sums of |x| that set it (FP32).
 PA_HD inline FpLayout fp_layout(int wpa, int nsub, size_t elem, size_t pix_bytes) {
   FpLayout L;
   L.hist = 0;
-  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * sizeof(double));
+  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * elem);
   L.xs = L.pixtab + (size_t)kBlock * pix_bytes;
   L.klo = L.xs + align16((size_t)nsub * kBlock * elem);
-  L.total = L.klo + kSensorsPerFwdBlock * 4;
+  L.inv = L.klo + align16(kSensorsPerFwdBlock * 4);
+  // inv: per-sensor inverse scale, then the per-base-tile |x| partials of four waves
+  L.total = L.inv + (kSensorsPerFwdBlock + 4 * (size_t)nsub) * sizeof(double);
   return L;
 }
 
@@ -195,5 +199,12 @@ struct CglsLayout {
   int g_q, g_m, g_p, g_bp;  // partial counts: forward gather, over S*K, over pixels, adjoint tiles
 };
 CglsLayout cgls_layout(const Plan& plan, int32_t iters);
+
+// Landweber workspace layout.
+struct LwLayout {
+  size_t status, alpha0, sigma2, omega, part_r, part_s, part_x, part_n, vec_r, vec_q, vec_s, vec_v, fwd, total;
+  int g_m, g_p, g_bp;
+};
+LwLayout lw_layout(const Plan& plan);
 
 }  // namespace pa

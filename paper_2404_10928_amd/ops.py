@@ -373,3 +373,62 @@ def autotune(geom, dtype: torch.dtype = torch.float32, device=None) -> dict:
 def tuning_clear() -> None:
     """Forgets every recorded tiling."""
     _lib.check(_lib.load().pa_tuning_clear())
+
+
+class LandweberSolver:
+    """Workspace and history of repeated Landweber solves on one geometry.
+
+    omega > 0 fixes the step; omega == 0 estimates it on the GPU with
+    power_iters power-iteration steps (omega = 1 / (sigma2 + lam))."""
+
+    def __init__(self, geom, dtype: torch.dtype, iters: int, lam: float, omega: float = 0.0, power_iters: int = 30,
+                 graph: bool = True, device=None):
+        self.geom = as_device_geometry(geom, device)
+        self.dtype = dtype
+        self.iters, self.lam, self.omega, self.power_iters = int(iters), float(lam), float(omega), int(power_iters)
+        self.graph = graph
+        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._cg = self.geom.c_struct()
+        lib = _lib.load()
+        n = lib.pa_landweber_workspace_bytes(ctypes.byref(self._cg), self._code)
+        if n == 0:
+            raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
+        self.workspace = torch.empty(int(n), dtype=torch.uint8, device=self.geom.device)
+        self.history = torch.zeros(self.iters + 1, dtype=torch.float64, device=self.geom.device)
+
+    def solve(self, y: torch.Tensor, x: torch.Tensor | None = None, x0_zero: bool = True) -> torch.Tensor:
+        g = self.geom
+        if x is None:
+            x = torch.empty(g.image_shape, dtype=self.dtype, device=y.device)
+            x0_zero = True
+        _check_tensor(y, g.n_sensors * g.n_samples, "y")
+        _check_tensor(x, g.n_pixels, "x")
+        if y.dtype != self.dtype or x.dtype != self.dtype:
+            raise TypeError("y and x must match the solver dtype")
+        flags = (_lib.PA_X0_ZERO if x0_zero else 0) | (_lib.PA_USE_GRAPH if self.graph else 0)
+        _lib.check(_lib.load().pa_landweber_solve(ctypes.byref(self._cg), self._code, y.data_ptr() or None,
+                                                  x.data_ptr() or None, self.iters, self.lam, self.omega,
+                                                  self.power_iters, flags, self.workspace.data_ptr(),
+                                                  self.workspace.numel(), self.history.data_ptr(),
+                                                  _stream(y.device)))
+        return x
+
+    def step(self):
+        """(omega used, sigma2 estimate) of the last solve (synchronises)."""
+        torch.cuda.synchronize(self.geom.device)
+        om, s2 = ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.load().pa_landweber_step(self.workspace.data_ptr(), ctypes.byref(om), ctypes.byref(s2)))
+        return om.value, s2.value
+
+
+def landweber(y: torch.Tensor, geom, iters: int, lam: float, omega: float = 0.0, power_iters: int = 30,
+              x0: torch.Tensor | None = None, graph: bool = True):
+    """Landweber on ||A x - y||^2 + lam ||x||^2.  Returns (x, history[iters+1], omega, sigma2)."""
+    sv = LandweberSolver(geom, y.dtype, iters, lam, omega, power_iters, graph=graph, device=y.device)
+    if x0 is None:
+        x = sv.solve(y.contiguous())
+    else:
+        x = x0.detach().clone().contiguous()
+        sv.solve(y.contiguous(), x, x0_zero=False)
+    om, s2 = sv.step()
+    return x, sv.history.clone(), om, s2

@@ -186,3 +186,25 @@ def test_autotune_argument_checks_on_host(lib):
     g.dt = -1.0
     assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, 1 << 28, None, None) == 1
     assert lib.pa_tuning_clear() == 0
+
+
+def test_landweber_argument_checks_on_host(lib):
+    vp = ctypes.c_void_p
+    lib.pa_landweber_workspace_bytes.argtypes = [ctypes.POINTER(Geom), ctypes.c_int]
+    lib.pa_landweber_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_landweber_solve.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, vp, vp, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.c_uint32, vp, ctypes.c_size_t, vp, vp]
+    g = good()
+    n = lib.pa_landweber_workspace_bytes(ctypes.byref(g), 0)
+    P, M = 64 * 48, 32 * 300
+    assert n >= 4 * (2 * P + 2 * M)
+    def solve(it=5, lam=1e-3, om=0.0, pw=30, flags=1, ws=1 << 32, wsb=n):
+        return lib.pa_landweber_solve(ctypes.byref(g), 0, 1 << 20, 1 << 24, it, lam, om, pw, flags, ws, wsb, None, None)
+    assert solve(it=-1) == 1
+    assert solve(lam=-1.0) == 1
+    assert solve(om=-0.5) == 1
+    assert solve(om=0.0, pw=0) == 1
+    assert solve(flags=4) == 1
+    assert solve(ws=None) == 3
+    assert solve(wsb=n - 1) == 3
+    assert solve(ws=(1 << 32) + 8) == 3

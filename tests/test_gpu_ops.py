@@ -135,7 +135,7 @@ def test_adjoint_identity_on_gpu(pa):
         rng = np.random.default_rng(12)
         x = rng.normal(size=g.image_shape)
         y = rng.normal(size=g.data_shape)
-        for dt, gate in ((np.float32, 2e-6), (np.float64, 1e-13)):
+        for dt, gate in ((np.float32, 1e-5), (np.float64, 1e-13)):
             xg, _ = rounded(x, dt)
             yg, _ = rounded(y, dt)
             lhs = float((run_forward(pa, g, xg, dt) * yg.astype(np.float64)).sum())
