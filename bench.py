@@ -71,6 +71,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle CGLS iterations timed on the host")
     ap.add_argument("--quick", action="store_true", help="skip operator and CPU legs (profiling runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-frames and 3D legs")
+    ap.add_argument("--no-tune", action="store_true", help="plan by rule instead of running the autotuner")
     ap.add_argument("--calib-copy-mib", type=int, default=64,
                     help="size of a plain device copy run once (counter calibration for profiling runs)")
     return ap.parse_args()
@@ -104,6 +105,9 @@ def main():
     y = torch.from_numpy(y_np.astype(np.float32)).to(dev)
     torch.cuda.synchronize()
     print(f"[bench] workload ready: P={P} S={S} K={K}", file=sys.stderr, flush=True)
+    # tilings for this shape from the autotuner (recorded for every later plan)
+    tuning = pa.autotune(geom, torch.float32) if not args.no_tune else None
+    print(f"[bench] tuning: {tuning}", file=sys.stderr, flush=True)
 
     # a plain copy of known size: HBM-counter calibration for profiling runs
     if args.calib_copy_mib > 0:
@@ -136,7 +140,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded vessel-tree phantom, y = A x + 1% Gaussian noise)",
         "config": {"workload": WORKLOAD, "image": [512, 512], "sensors": S, "samples": K,
-                   "cgls_iterations": w.iters, "step": "one full CGLS solve (graph replay)"},
+                   "cgls_iterations": w.iters, "step": "one full CGLS solve (graph replay)",
+                   "tuning": tuning},
     }
 
     if not args.quick:
@@ -224,9 +229,10 @@ def main():
                   file=sys.stderr, flush=True)
 
     if not args.quick and not args.no_extras:
-        out["batched_frames"] = batched_leg(pa, torch, dev)
-        out["volume_3d"] = volume_leg(pa, torch, dev)
+        out["batched_frames"] = batched_leg(pa, torch, dev, tune=not args.no_tune)
+        out["volume_3d"] = volume_leg(pa, torch, dev, tune=not args.no_tune)
         out["landweber"] = landweber_leg(pa, torch, dev, geom, y, w)
+        out["differentiable"] = autograd_leg(pa, torch, dev)
 
     print(json.dumps(out))
     return 0
@@ -241,13 +247,16 @@ def _sync_time(torch, fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def batched_leg(pa, torch, dev):
+def batched_leg(pa, torch, dev, tune=True):
     """64 uneven frames (images 128-512, 64-512 sensors, 512-2048 samples),
     50 CGLS iterations: one batched graph replay against 64 single-frame
     graph replays, with the largest per-frame iterate difference."""
     from synth import add_noise, make_config
     w = make_config("C4")
     geoms = [pa.DeviceGeometry(g, dev) for g in w.geoms]
+    if tune:   # every frame shape, before the batch is planned
+        for g in geoms:
+            pa.autotune(g, torch.float32)
     b = pa.Batch(geoms, torch.float32, dev)
     xp = b.pack_x([torch.from_numpy(x.astype(np.float32)).to(dev) for x in w.x_true])
     yc = b.unpack_y(b.forward(xp))
@@ -290,7 +299,31 @@ def landweber_leg(pa, torch, dev, geom, y, w):
             "F_first": float(sv.history[0]), "F_last": float(sv.history[-1])}
 
 
-def volume_leg(pa, torch, dev):
+def autograd_leg(pa, torch, dev):
+    """Loss ||A x - y||^2 + 1e-3 TV(x) over 16 images of 256x256 (128-sensor
+    ring, 1024 samples), forward and backward through the autograd wrapper:
+    one batched launch per operator pass."""
+    import paper_2404_10928_amd.autograd as ag
+    from synth import make_config
+    w = make_config("C3")
+    g = pa.DeviceGeometry(w.geom, dev)
+    X = torch.from_numpy(np.stack(w.x_true).astype(np.float32)).to(dev).requires_grad_(True)
+    Y = torch.zeros((len(w.x_true),) + g.data_shape, dtype=torch.float32, device=dev)
+    with torch.no_grad():
+        Y.copy_(ag.PAForward.apply(X, g))
+
+    def step():
+        X.grad = None
+        loss = ag.data_term(X * 0.9, Y, g) + 1e-3 * ag.tv(X)
+        loss.backward()
+
+    step()
+    t = _sync_time(torch, step, 5)
+    return {"workload": "16 images of 256x256, 128-sensor ring, 1024 samples; loss ||Ax - y||^2 + 1e-3 TV(x), FP32",
+            "ms_per_forward_backward": t * 1e3, "images_per_s": len(w.x_true) / t}
+
+
+def volume_leg(pa, torch, dev, tune=True):
     """128^3 voxels, 1024-sensor hemisphere, 2048 samples, 30 CGLS iterations
     in FP32 (FP64 reductions) and in FP64, timed, with their iterate gap."""
     from synth import add_noise, make_config
@@ -303,6 +336,8 @@ def volume_leg(pa, torch, dev):
                        f"{w.iters} CGLS iterations"}
     xs = {}
     for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        if tune:
+            res[f"tuning_{name}"] = pa.autotune(g, dt)
         sv = pa.CglsSolver(g, dt, w.iters, w.lam, graph=True, device=dev)
         y = y32.to(dt)
         x = torch.empty(g.image_shape, dtype=dt, device=dev)

@@ -149,11 +149,13 @@ pa_status pa_landweber_step(const void* workspace, double* omega, double* sigma2
  * traces sit in packed buffers at the element offsets pa_batch_offsets()
  * gives (the frames one after another, in the order passed to
  * pa_batch_create).  The batched kernels run the single-frame device code on
- * each frame's own plan and form every partial sum in the same order, so the
- * adjoint and the solver steps give each frame its single-frame result bit
- * for bit.  The forward operator's FP64 histogram adds run in hardware order
- * (in single-frame calls as well), so forward results agree to the rounding
- * of those sums, and solves to that rounding as CG propagates it.
+ * each frame's own plan and form every partial sum in the same order, so a
+ * frame gets its single-frame result bit for bit in PA_F32 (whose forward
+ * operator sums integers) and, in PA_F64, to the rounding of the forward
+ * operator's FP64 histogram adds, which run in hardware order in every call.
+ * (A frame whose autotuned tiling would raise the LDS of the whole batched
+ * launch above what the planner's rules give is planned by rule; it then
+ * matches a single-frame call planned by rule.)
  */
 typedef struct pa_batch pa_batch;
 
@@ -202,13 +204,14 @@ pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int
  * The planner picks the forward operator's tile (base tiles per forward
  * tile) and the adjoint's sensor chunk (from an LDS budget) by rule.
  * pa_autotune times each candidate tiling of both operators on this
- * geometry and records the fastest in a process-wide table keyed by shape
- * (ndim, dtype, nx, ny, nz, S, K and h / (c dt)); every later call on a
- * geometry of that shape, batches included, plans with the recorded tiling.
- * Tilings change only the order of floating-point sums, not the operator.
- * x, y: device buffers of the geometry's image and trace sizes, used as
- * scratch (their contents are overwritten).  Synchronises the stream.  May
- * allocate the forward operator's internal scratch (as pa_forward does). */
+ * geometry (best of three runs of eight launches) and records the fastest
+ * in a process-wide table keyed by shape (ndim, dtype, nx, ny, nz, S, K and
+ * h / (c dt)); every later call on a geometry of that shape, batches
+ * included, plans with the recorded tiling.  Tilings change only the order
+ * of floating-point sums, not the operator.  x, y: device buffers of the
+ * geometry's image and trace sizes, used as scratch (their contents are
+ * overwritten).  Synchronises the stream.  May allocate the forward
+ * operator's internal scratch (as pa_forward does). */
 typedef struct {
   int32_t fwd_tile[3];     /* base tiles per forward tile, per axis (0: no forward work) */
   int32_t adj_lds_bytes;   /* adjoint LDS budget that sets its sensor chunk (0: no adjoint work) */

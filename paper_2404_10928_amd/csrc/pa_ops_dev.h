@@ -376,13 +376,29 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
       }
     }
     __syncthreads();
-    const int tot = nsc * P.wp;
-    for (int e = tid; e < tot; e += kBlock) {
-      const int j = (int)__umulhi((unsigned)e, P.wp_magic);
-      const int k = klo_s[j] + (e - j * P.wp);
-      T v = 0;
-      if (k >= 0 && k < P.K) v = y[(size_t)sid[j] * P.K + k];
-      win[e] = v;
+    // Stage the windows: wave w copies rows w, w+4, ... (row parameters are
+    // wave-uniform), four rows' loads in flight before their stores.
+    for (int i0 = 0; i0 < P.wp; i0 += 64) {
+      const int i = i0 + lane;
+      for (int j0 = wave; j0 < nsc; j0 += 16) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + 4 * u;
+          v[u] = 0;
+          if (j < nsc) {
+            const int kl = __builtin_amdgcn_readfirstlane(klo_s[j]);
+            const int sj = __builtin_amdgcn_readfirstlane(sid[j]);
+            const int k = kl + i;
+            if (i < P.wp && k >= 0 && k < P.K) v[u] = y[(size_t)sj * P.K + k];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + 4 * u;
+          if (j < nsc && i < P.wp) win[j * P.wp + i] = v[u];
+        }
+      }
     }
     __syncthreads();
     // Sensors whose arrivals miss the trace carry zero weight and a bounded
@@ -460,8 +476,9 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
 
 // ---------------------------------------------------------------------------
 // A, pass 1: one work-group per (forward tile, chunk of 64 sensors); lane =
-// sensor, wave w walks base tiles w, w+4, ... of the forward tile one pixel at
-// a time (the pixel is uniform across the wave).  Each lane scatters its two
+// sensor, wave w walks base tiles w, w+4, ... of the forward tile (or, with
+// fewer than four base tiles, a quarter or half of one) one pixel at a time
+// (the pixel is uniform across the wave).  Each lane scatters its two
 // taps into its own sensor's LDS histogram row, so the lanes of one ds_add
 // never collide on an address.  The rows are then written out with plain
 // coalesced stores, with the first sample of each row in a table.
@@ -577,7 +594,12 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
   __syncthreads();
 
   const float t0f = P.t0f;
-  for (int m = wave; m < P.nsub; m += 4) {
+  // Work items: (base tile m, part).  With fewer than four base tiles per
+  // forward tile the waves split each tile's pixels into `parts` ranges.
+  const int parts = P.nsub >= 4 ? 1 : 4 / P.nsub;
+  for (int item = wave; item < P.nsub * parts; item += 4) {
+    const int m = item / parts;
+    const int part = item - m * parts;
     const int bx = ax * P.msub[0] + m % P.msub[0];
     const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
     const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
@@ -601,13 +623,15 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
     // pixel's constants are read before this pixel's LDS adds are issued, so
     // the adds never hold up the reads.
     constexpr int NPIX = TX * TY * TZ;
-    PX pn = pixtab[0];
-    T xn = xm[0];
+    const int p_lo = part * (NPIX / parts);
+    const int p_hi = p_lo + NPIX / parts;
+    PX pn = pixtab[p_lo];
+    T xn = xm[p_lo];
 #pragma unroll 2
-    for (int p = 0; p < NPIX; ++p) {
+    for (int p = p_lo; p < p_hi; ++p) {
       const PX px = pn;
       const T xp = xn;
-      const int pq = p + 1 < NPIX ? p + 1 : p;
+      const int pq = p + 1 < p_hi ? p + 1 : p;
       pn = pixtab[pq];
       xn = xm[pq];
       int kb;
@@ -628,7 +652,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
       }
     }
     if constexpr (F32) {
-      uint64_t nm = __ballot(near);
+      uint64_t nm = part == 0 ? __ballot(near) : 0;  // the near pairs of tile m, once
       if (nm != 0) {
         const double rmin2 = P.rmin * P.rmin;
         // this lane's row base for its own sensor, as the far constants would have it

@@ -202,7 +202,6 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     int64_t S = std::max<int64_t>(g->n_sensors, 1);
     int64_t nchunk = (S + sc_max - 1) / sc_max;
     op.sc = (int32_t)((S + nchunk - 1) / nchunk);
-    op.wp_magic = (uint32_t)(((uint64_t)1 << 32) / (uint64_t)op.wp + 1);
     pl.bp_lds = bp_layout(op.sc, op.wp, elem, sc_bytes, near_bytes).total;
     if (pl.bp_lds > kLdsMax) return fail(msg, PA_ERR_UNSUPPORTED, "adjoint LDS plan exceeds 160 KiB");
   }
@@ -341,15 +340,31 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
   B.nf = n_frames;
   B.dtype = dtype;
   B.plans.resize(n_frames);
+  // A batched launch gives every work-group the largest LDS any frame needs,
+  // so a frame keeps its tuned tiling only if that stays within what the
+  // planner's rules give for the batch; otherwise it is planned by rule.
+  std::vector<Plan> rule(n_frames);
+  size_t rule_bp = 0, rule_fp = 0;
+  const Tuning by_rule{{0, 0, 0}, 0};
   for (int i = 0; i < n_frames; ++i) {
     std::string m;
-    pa_status st = make_plan(&frames[i], dtype, &B.plans[i], &m);
+    pa_status st = make_plan(&frames[i], dtype, &rule[i], &m, &by_rule);
     if (st != PA_OK) {
       if (msg) *msg = "frame " + std::to_string(i) + ": " + m;
       return st;
     }
     if (i > 0 && frames[i].ndim != frames[0].ndim)
       return fail(msg, PA_ERR_INVALID_ARGUMENT, "every frame of a batch must have the same ndim");
+    rule_bp = std::max(rule_bp, rule[i].bp_lds);
+    rule_fp = std::max(rule_fp, rule[i].fp_lds);
+  }
+  for (int i = 0; i < n_frames; ++i) {
+    std::string m;
+    Plan tuned;
+    if (make_plan(&frames[i], dtype, &tuned, &m) == PA_OK && tuned.bp_lds <= rule_bp && tuned.fp_lds <= rule_fp)
+      B.plans[i] = tuned;
+    else
+      B.plans[i] = rule[i];
   }
   B.ndim = frames[0].ndim;
   B.elem = B.plans[0].elem;

@@ -51,7 +51,6 @@ struct OpParams {
   int32_t n_tiles;          // product
   int32_t wp;               // adjoint: LDS window stride (samples) of one sensor
   int32_t sc;               // adjoint: sensors staged per chunk
-  uint32_t wp_magic;        // ceil(2^32 / wp) for index division
   int32_t msub[3];          // forward: base tiles per forward tile, per axis
   int32_t nsub;             // product
   int32_t natile[3];        // forward tiles per axis

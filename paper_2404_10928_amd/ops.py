@@ -100,8 +100,23 @@ def _frames(t: torch.Tensor, per: int):
     return list(t.reshape(nb, per)), nb
 
 
+_BATCHES: dict = {}
+
+
+def _frames_batch(g: "DeviceGeometry", n: int, dtype: torch.dtype) -> "Batch":
+    """A cached batch of n copies of one geometry (frames of a leading batch dimension)."""
+    key = (id(g), n, dtype)
+    b = _BATCHES.get(key)
+    if b is None or b.geoms[0] is not g:
+        if len(_BATCHES) > 32:
+            _BATCHES.clear()
+        b = _BATCHES[key] = Batch([g] * n, dtype, g.device)
+    return b
+
+
 def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Tensor:
-    """y := A x.  Leading batch dimensions of x are applied frame by frame."""
+    """y := A x.  Leading batch dimensions of x are frames, applied in one
+    batched launch per pass (the single-frame result for every frame)."""
     g = as_device_geometry(geom, x.device)
     P, M = g.n_pixels, g.n_sensors * g.n_samples
     x = x.contiguous()
@@ -113,6 +128,9 @@ def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Ten
     ys, nb2 = _frames(out, M) if M else ([out.reshape(-1)] * len(xs), nb)
     if M and len(xs) != len(ys):
         raise ValueError("x and y hold different numbers of frames")
+    if len(xs) > 1 and P and M:
+        _frames_batch(g, len(xs), x.dtype).forward(x.reshape(-1), out.reshape(-1))
+        return out
     lib = _lib.load()
     cg = g.c_struct()
     for xb, yb in zip(xs, ys):
@@ -122,7 +140,8 @@ def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Ten
 
 
 def adjoint(y: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Tensor:
-    """x := A^T y.  Leading batch dimensions of y are applied frame by frame."""
+    """x := A^T y.  Leading batch dimensions of y are frames, applied in one
+    batched launch (the single-frame result for every frame)."""
     g = as_device_geometry(geom, y.device)
     P, M = g.n_pixels, g.n_sensors * g.n_samples
     y = y.contiguous()
@@ -134,6 +153,9 @@ def adjoint(y: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Ten
     xs, nb2 = _frames(out, P) if P else ([out.reshape(-1)] * len(ys), nb)
     if P and len(xs) != len(ys):
         raise ValueError("x and y hold different numbers of frames")
+    if len(ys) > 1 and P and M:
+        _frames_batch(g, len(ys), y.dtype).adjoint(y.reshape(-1), out.reshape(-1))
+        return out
     lib = _lib.load()
     cg = g.c_struct()
     for yb, xb in zip(ys, xs):

@@ -80,7 +80,11 @@ def test_landweber_graph_eager_and_edges(pa):
     y = torch.from_numpy(rng.normal(size=g.data_shape)).to("cuda")
     xa, ha, oa, _ = pa.landweber(y, g, 6, 1e-2, omega=0.0, power_iters=10, graph=True)
     xb, hb, ob, _ = pa.landweber(y, g, 6, 1e-2, omega=0.0, power_iters=10, graph=False)
-    assert oa == ob and torch.equal(xa, xb) and torch.equal(ha, hb)
+    # the FP64 forward operator adds its histogram terms in hardware order, so
+    # two runs agree to FP64 rounding, not bit for bit
+    assert abs(oa / ob - 1) <= 1e-13
+    assert rel_l2(xa.cpu().numpy(), xb.cpu().numpy()) <= 1e-12
+    np.testing.assert_allclose(ha.cpu().numpy(), hb.cpu().numpy(), rtol=1e-12)
     # zero iterations: history holds F(x0) only
     x0 = torch.from_numpy(rng.uniform(size=g.image_shape)).to("cuda")
     x, h, _, _ = pa.landweber(y, g, 0, 1e-2, omega=1e-3, x0=x0)
