@@ -165,6 +165,19 @@ typedef struct pa_batch pa_batch;
  * a handle to free with pa_batch_destroy. */
 pa_status pa_batch_create(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, pa_batch** out);
 
+/* A batch is planned by the planner's rules.  pa_batch_autotune times the
+ * batched A and A^T under those plans and under the frames' recorded tunings
+ * (pa_autotune; a tuned frame whose LDS would exceed the rule plans' maximum
+ * stays on its rule plan) and keeps the faster set; *tuned (may be NULL) is 1
+ * when the tuned plans were kept.  x, y: packed scratch buffers of the batch's
+ * sizes (overwritten); workspace: pa_batch_autotune_workspace_bytes() bytes
+ * (a candidate needing more than the given size is skipped).  Synchronises
+ * the stream.  Query pa_batch_workspace_bytes / pa_batch_cgls_workspace_bytes
+ * again afterwards: the plan may have changed. */
+size_t pa_batch_autotune_workspace_bytes(const pa_batch* b);
+pa_status pa_batch_autotune(pa_batch* b, void* x, void* y, void* workspace, size_t workspace_bytes,
+                            void* hip_stream, int32_t* tuned);
+
 /* Frees the handle (and the page-locked host copy of its frame table).  The
  * caller must have synchronised every stream that used it.  NULL is a no-op. */
 pa_status pa_batch_destroy(pa_batch* b);

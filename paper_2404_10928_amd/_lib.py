@@ -32,7 +32,8 @@ EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspac
            "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version", "pa_batch_create", "pa_batch_destroy",
            "pa_batch_offsets", "pa_batch_workspace_bytes", "pa_batch_cgls_workspace_bytes", "pa_batch_forward",
            "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations", "pa_autotune", "pa_tuning_clear",
-           "pa_landweber_workspace_bytes", "pa_landweber_solve", "pa_landweber_step"]
+           "pa_landweber_workspace_bytes", "pa_landweber_solve", "pa_landweber_step",
+           "pa_batch_autotune_workspace_bytes", "pa_batch_autotune"]
 
 
 class PaTuning(ctypes.Structure):
@@ -113,6 +114,10 @@ def load(path: str = LIB_PATH):
     dpp = ctypes.POINTER(ctypes.c_double)
     lib.pa_landweber_step.argtypes = [vp, dpp, dpp]
     lib.pa_landweber_step.restype = ctypes.c_int
+    lib.pa_batch_autotune_workspace_bytes.argtypes = [vp]
+    lib.pa_batch_autotune_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_batch_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.pa_batch_autotune.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -319,6 +319,7 @@ hipError_t get_scratch(size_t bytes, hipStream_t st, void** out) {
 
 struct pa_batch {
   pa::BatchPlan plan;
+  std::vector<pa_geometry> frames;   // the caller's geometries (device sensor pointers are theirs)
   pa::FrameDesc* pinned = nullptr;   // page-locked copy of plan.table (allocated on first use)
   uint64_t id = 0;
   std::mutex mu;
@@ -575,8 +576,100 @@ pa_status pa_batch_create(const pa_geometry* frames, int32_t n_frames, pa_dtype 
   pa_batch* b = new (std::nothrow) pa_batch();
   if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "out of host memory");
   b->plan = std::move(B);
+  b->frames.assign(frames, frames + n_frames);
   b->id = g_batch_ids.fetch_add(1);
   *out = b;
+  return PA_OK;
+}
+
+size_t pa_batch_autotune_workspace_bytes(const pa_batch* b) {
+  g_err.clear();
+  if (!b) {
+    set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+    return 0;
+  }
+  size_t n = 0;
+  for (int c = 0; c < 2; ++c) {
+    pa::BatchPlan B;
+    std::string msg;
+    if (pa::make_batch_plan(b->frames.data(), (int32_t)b->frames.size(), b->plan.dtype, &B, &msg, c == 1) != PA_OK) {
+      set_err(PA_ERR_INVALID_ARGUMENT, msg);
+      return 0;
+    }
+    n = std::max(n, pa::batch_layout(B, 0, false).total);
+  }
+  return n;
+}
+
+pa_status pa_batch_autotune(pa_batch* b, void* x, void* y, void* workspace, size_t workspace_bytes,
+                            void* hip_stream, int32_t* tuned) {
+  g_err.clear();
+  if (!b) return set_err(PA_ERR_INVALID_ARGUMENT, "batch is NULL");
+  pa::BatchPlan cand[2];
+  std::string msg;
+  for (int c = 0; c < 2; ++c) {
+    pa_status st = pa::make_batch_plan(b->frames.data(), (int32_t)b->frames.size(), b->plan.dtype, &cand[c], &msg,
+                                       c == 1);
+    if (st != PA_OK) return set_err(st, msg);
+  }
+  pa_status st;
+  if ((st = check_batch_vecs(b, x, y, workspace, workspace_bytes)) != PA_OK) return st;
+  if (!workspace || !aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is NULL or misaligned");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PA_HIP(hipEventCreate(&e0), "hipEventCreate");
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_err(he, "hipEventCreate");
+  }
+  float best = 3.0e38f;
+  int pick = 0;
+  hipError_t err = hipSuccess;
+  for (int c = 0; c < 2 && err == hipSuccess; ++c) {
+    const pa::BatchLayout L = pa::batch_layout(cand[c], 0, false);
+    if (L.total > workspace_bytes) continue;  // this candidate needs a larger workspace
+    const size_t tb = sizeof(pa::FrameDesc) * cand[c].table.size();
+    // the table goes through a synchronous copy here (the stream is synchronised below anyway)
+    if ((err = hipStreamSynchronize(s)) != hipSuccess) break;
+    if ((err = hipMemcpy(ws + L.table, cand[c].table.data(), tb, hipMemcpyHostToDevice)) != hipSuccess) break;
+    const pa::BatchLaunch bl = batch_launch(cand[c], ws, L);
+    auto run = [&]() -> hipError_t {
+      hipError_t e = pa::launch_forward_batched(bl, x, y, nullptr, s);
+      if (e != hipSuccess) return e;
+      return pa::launch_adjoint_batched(bl, y, x, nullptr, s);
+    };
+    if ((err = run()) != hipSuccess) break;
+    float t = 3.0e38f;
+    for (int trial = 0; trial < 3 && err == hipSuccess; ++trial) {
+      if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+      for (int r = 0; r < 3 && err == hipSuccess; ++r) err = run();
+      if (err != hipSuccess) break;
+      if ((err = hipEventRecord(e1, s)) != hipSuccess) break;
+      if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      t = std::min(t, ms);
+    }
+    if (err == hipSuccess && t < best) {
+      best = t;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_err(err, "batch autotune");
+  if (best == 3.0e38f) return set_err(PA_ERR_WORKSPACE, "workspace too small for every candidate plan");
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->plan = std::move(cand[pick]);
+    if (b->pinned) {
+      (void)hipHostFree(b->pinned);
+      b->pinned = nullptr;
+    }
+  }
+  if (tuned) *tuned = pick;
   return PA_OK;
 }
 

@@ -331,7 +331,7 @@ LwLayout lw_layout(const Plan& plan) {
 }
 
 pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, BatchPlan* bp,
-                          std::string* msg) {
+                          std::string* msg, bool use_tuning) {
   if (!bp) return fail(msg, PA_ERR_INVALID_ARGUMENT, "batch plan pointer is NULL");
   if (n_frames < 1) return fail(msg, PA_ERR_INVALID_ARGUMENT, "a batch needs at least one frame");
   if (!frames) return fail(msg, PA_ERR_INVALID_ARGUMENT, "frame array is NULL");
@@ -341,8 +341,8 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
   B.dtype = dtype;
   B.plans.resize(n_frames);
   // A batched launch gives every work-group the largest LDS any frame needs,
-  // so a frame keeps its tuned tiling only if that stays within what the
-  // planner's rules give for the batch; otherwise it is planned by rule.
+  // so with use_tuning a frame keeps its tuned tiling only if that stays
+  // within what the planner's rules give for the batch.
   std::vector<Plan> rule(n_frames);
   size_t rule_bp = 0, rule_fp = 0;
   const Tuning by_rule{{0, 0, 0}, 0};
@@ -361,11 +361,13 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
   for (int i = 0; i < n_frames; ++i) {
     std::string m;
     Plan tuned;
-    if (make_plan(&frames[i], dtype, &tuned, &m) == PA_OK && tuned.bp_lds <= rule_bp && tuned.fp_lds <= rule_fp)
+    if (use_tuning && make_plan(&frames[i], dtype, &tuned, &m) == PA_OK && tuned.bp_lds <= rule_bp &&
+        tuned.fp_lds <= rule_fp)
       B.plans[i] = tuned;
     else
       B.plans[i] = rule[i];
   }
+  B.tuned = use_tuning;
   B.ndim = frames[0].ndim;
   B.elem = B.plans[0].elem;
   // packed buffers in caller order

@@ -175,10 +175,13 @@ struct BatchPlan {
   size_t bp_lds = 0, fp_lds = 0, gather_lds = 0;
   size_t fwd_scratch = 0;
   int64_t P_total = 0, M_total = 0;
+  bool tuned = false;             // planned with the recorded per-frame tunings
 };
 
+// use_tuning: plan frames with their recorded tunings (capped so the batch's
+// LDS stays within its rule plans' maximum) instead of by rule.
 pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, BatchPlan* bp,
-                          std::string* msg);
+                          std::string* msg, bool use_tuning = false);
 
 // Workspace of batched calls: the device frame table, the forward scratch
 // and (cg) the per-frame CGLS state for `iters` iterations, partials and vectors.

@@ -367,6 +367,22 @@ class Batch:
         self._last_iters = iters
         return x
 
+    def autotune(self) -> bool:
+        """Times the batched operators under rule plans and under the frames'
+        recorded tunings and keeps the faster; True if the tuned plans won."""
+        n = int(self._lib.pa_batch_autotune_workspace_bytes(self._h))
+        if n == 0:
+            raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
+        ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        x = torch.zeros(self.x_offsets[-1], dtype=self.dtype, device=self.device)
+        y = torch.zeros(self.y_offsets[-1], dtype=self.dtype, device=self.device)
+        out = ctypes.c_int32(0)
+        _lib.check(self._lib.pa_batch_autotune(self._h, x.data_ptr() or None, y.data_ptr() or None, ws.data_ptr(),
+                                               ws.numel(), _stream(self.device), ctypes.byref(out)))
+        self._ws = None       # the plan may need other workspace sizes now
+        self._ws_cg = {}
+        return bool(out.value)
+
     def stop_iterations(self) -> list:
         """Per frame: the iteration its last solve stopped at, or -1 (synchronises)."""
         torch.cuda.synchronize(self.device)

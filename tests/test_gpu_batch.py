@@ -179,8 +179,12 @@ def test_autotune_records_a_tiling_and_keeps_results(pa):
     # another tiling changes only the order of sums
     assert rel_l2(after_f, before_f) <= 1e-6 and rel_l2(after_a, before_a) <= 1e-6
     assert rel_l2(after_f, oracle.forward(g, x64)) <= 1e-5 and rel_l2(after_a, oracle.adjoint(g, y64)) <= 1e-5
-    # a batch of frames of the tuned shape plans with the recorded tiling too
+    # a batch times its rule plans against the frames' tuned plans and keeps the faster
     b = pa.Batch([g, ring_geom(n=(40, 40), S=20, K=200)], torch.float32)
+    kept_tuned = b.autotune()
+    print("batch kept tuned plans:", kept_tuned)
     yb = b.unpack_y(b.forward(b.pack_x([torch.from_numpy(x).to("cuda"), torch.zeros((40, 40), device="cuda")])))
     assert rel_l2(yb[0].cpu().numpy(), oracle.forward(g, x64)) <= 1e-5
+    xb = b.unpack_x(b.adjoint(b.pack_y([torch.from_numpy(y).to("cuda"), torch.zeros((20, 200), device="cuda")])))
+    assert rel_l2(xb[0].cpu().numpy(), oracle.adjoint(g, y64)) <= 1e-5
     pa.tuning_clear()
