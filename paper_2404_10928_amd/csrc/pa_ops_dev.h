@@ -17,7 +17,6 @@ namespace {
 using dev::block_sum;
 
 
-constexpr float kInactiveCmin = 1.0f;
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   // Work-groups are dealt round-robin to the 8 XCDs (block b -> XCD b % 8).
@@ -46,7 +45,7 @@ struct SC32 {
   float KRN;    // -kr
   float KR2N;   // -2 kr
   float KR2;    // kr^2
-  float CMIN;   // rmin^2 - kr^2 (distance clamp, in num units)
+  float pad0;   // (far pairs never reach the distance clamp: see the near test)
   int BASE;     // byte offset of sample (kr - t0i) in this sensor's LDS row
   int act;      // 0: sensor contributes nothing to this tile
   float HALF;   // 0.5 (active) or 0 (inactive): weight multiplier
@@ -148,9 +147,9 @@ __device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], 
   double dx = ref[0] - sp[0], dy = ref[1] - sp[1], dz = ND == 3 ? ref[2] - sp[2] : 0.0;
   double ra2 = dx * dx + dy * dy + dz * dz;
   double kr = rint(sqrt(ra2));
-  if (!active) {  // benign constants: bounded delay, zero weight
-    c.E = 0.f; c.DX2 = 0.f; c.DY2 = 0.f; c.DZ2 = 0.f; c.KRN = 0.f; c.KR2N = 0.f; c.KR2 = 0.f;
-    c.CMIN = kInactiveCmin; c.BASE = row_elems * esz; c.act = 0; c.HALF = 0.f;
+  if (!active) {  // benign constants: num = |o|^2 + 1 >= 1, a delay of at most |o| + 1, zero weight
+    c.E = 1.f; c.DX2 = 0.f; c.DY2 = 0.f; c.DZ2 = 0.f; c.KRN = 0.f; c.KR2N = 0.f; c.KR2 = 0.f;
+    c.pad0 = 0.f; c.BASE = row_elems * esz; c.act = 0; c.HALF = 0.f;
     return;
   }
   c.E = (float)(ra2 - kr * kr);
@@ -160,7 +159,7 @@ __device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], 
   c.KRN = (float)(-kr);
   c.KR2N = (float)(-2.0 * kr);
   c.KR2 = (float)(kr * kr);
-  c.CMIN = (float)(P.rmin * P.rmin - kr * kr);
+  c.pad0 = 0.f;
   c.BASE = ((int)kr - P.t0i - klo + row_elems) * esz;
   c.act = 1;
   c.HALF = 0.5f;
@@ -200,7 +199,6 @@ __device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f,
   float num = fmaf(px.oy, c.DY2, t);
   if (ND == 3) num = fmaf(px.oz, c.DZ2, num);
   num = fmaf(px.ox, c.DX2, num);
-  num = fmaxf(num, c.CMIN);
   const float R2 = num + c.KR2;
   const float w = __builtin_amdgcn_rsqf(R2);
   const float da = fmaf(R2, w, c.KRN);       // R - kr, FP32 estimate
@@ -706,21 +704,18 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
 }
 
 // A, pass 2: one work-group per (sensor, segment of kseg <= 256 samples),
-// one sample per lane.  The work-group lists, in increasing order, the
-// forward tiles whose row window overlaps its segment, then every lane adds
-// its sample of those rows in list order in FP64, scales, and writes y, with
-// the FP64 partial of ||y||^2.  No atomics: the result is the same on every
-// run.  Rows and window starts are sensor-major, so one sensor's rows are
-// contiguous.
+// one sample per lane.  Each wave scans the window starts of the sensor's
+// forward tiles, 64 at a time, picks by ballot the tiles whose row window
+// overlaps its own 64 samples, and every lane adds its sample of those rows,
+// in increasing tile order, in FP64 (eight loads in flight); then the
+// work-group scales, writes y and forms the FP64 partial of ||y||^2.  No
+// atomics: the result is the same on every run.  Rows and window starts are
+// sensor-major, so one sensor's rows are contiguous.
 template <typename T>
 __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx, const T* __restrict__ rows,
                                             const int* __restrict__ klo_tab, T* __restrict__ y,
                                             double* __restrict__ part_q) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  int* list = reinterpret_cast<int*>(smem);               // kGatherChunk tile indices
-  int* lkl = list + kGatherChunk;                          // their window starts
   __shared__ double red[4];
-  __shared__ int wcount[4];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -729,70 +724,42 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
   const int k0 = seg * P.kseg;
   const int kn = min(P.kseg, P.K - k0);
   const int k = k0 + tid;
+  const bool k_ok = tid < kn;
   const int* kt = klo_tab + (size_t)s * P.n_atiles;
   const T* srow = rows + (size_t)s * P.n_atiles * P.wpa;
-  // the part of the segment this wave's lanes cover
-  const int wlo = k0 + wave * 64, whi = min(k0 + kn, wlo + 64);
+  const int wlo = k0 + wave * 64, whi = min(k0 + kn, wlo + 64);  // this wave's samples
   double acc = 0.0;
-  for (int c0 = 0; c0 < P.n_atiles; c0 += kGatherChunk) {
-    const int nc = min(kGatherChunk, P.n_atiles - c0);
-    // compaction: wave w tests tiles c0 + w * (kGatherChunk / 4) + [0, kGatherChunk / 4)
-    constexpr int PER = kGatherChunk / 4;
-    uint64_t masks[PER / 64];
-    int kls[PER / 64];
-    int n = 0;
-#pragma unroll
-    for (int g = 0; g < PER / 64; ++g) {
-      const int at = wave * PER + g * 64 + lane;
+  if (wlo < whi) {
+    for (int c0 = 0; c0 < P.n_atiles; c0 += 64) {
+      const int t = c0 + lane;
       int kl = 0;
       bool ov = false;
-      if (at < nc) {
-        kl = kt[c0 + at];
-        ov = kl < k0 + kn && kl + P.wpa > k0;
+      if (t < P.n_atiles) {
+        kl = kt[t];
+        ov = kl < whi && kl + P.wpa > wlo;
       }
-      masks[g] = __ballot(ov);
-      kls[g] = kl;
-      n += __popcll(masks[g]);
-    }
-    if (lane == 0) wcount[wave] = n;
-    __syncthreads();
-    int base = 0;
-    for (int w = 0; w < wave; ++w) base += wcount[w];
-    const int total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+      uint64_t m = __ballot(ov);
+      while (m != 0) {
+        double v[8];
 #pragma unroll
-    for (int g = 0; g < PER / 64; ++g) {
-      const uint64_t m = masks[g];
-      if ((m >> lane) & 1) {
-        const int pos = base + __popcll(m & ((1ull << lane) - 1));
-        list[pos] = c0 + wave * PER + g * 64 + lane;
-        lkl[pos] = kls[g];
-      }
-      base += __popcll(m);
-    }
-    __syncthreads();
-    // accumulate the listed rows, eight loads in flight at a time
-    for (int i0 = 0; i0 < total; i0 += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        v[u] = 0.0;
-        const int i = i0 + u;
-        if (i < total) {
-          const int kl = lkl[i];
-          if (kl < whi && kl + P.wpa > wlo) {  // wave-uniform
-            const int j = k - kl;
-            if (j >= 0 && j < P.wpa && k < k0 + kn) v[u] = (double)srow[(size_t)list[i] * P.wpa + j];
+        for (int u = 0; u < 8; ++u) {
+          v[u] = 0.0;
+          if (m != 0) {  // wave-uniform
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            const int klb = __builtin_amdgcn_readlane(kl, b);
+            const int j = k - klb;
+            if (k_ok && j >= 0 && j < P.wpa) v[u] = (double)srow[(size_t)(c0 + b) * P.wpa + j];
           }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc += v[u];
+        for (int u = 0; u < 8; ++u) acc += v[u];
+      }
     }
-    __syncthreads();  // the list is rebuilt for the next chunk
   }
   const double scale = sizeof(T) == 4 ? 2.0 * P.inv_cdt : P.out_scale_d;
   double q = 0.0;
-  if (tid < kn) {
+  if (k_ok) {
     const T out = (T)(acc * scale);
     y[(size_t)s * P.K + k] = out;
     q = (double)out * (double)out;

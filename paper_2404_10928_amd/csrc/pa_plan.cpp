@@ -175,11 +175,13 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
 
   // Sensors closer than three base-tile half-diagonals to a tile centre take
   // the FP64 delay path in the FP32 kernels (the tile-local FP32 form loses
-  // relative precision in R^2 when R is small against the tile size).
+  // relative precision in R^2 when R is small against the tile size).  The
+  // radius also covers r_min + a half-diagonal, so every pixel of a far pair
+  // is more than r_min from its sensor and the FP32 path needs no clamp.
   {
     double ex = (TX - 1) * hs, ey = (TY - 1) * hs, ez = (TZ - 1) * hs;
     double hd = 0.5 * std::sqrt(ex * ex + ey * ey + ez * ez);
-    double nr = 3.0 * hd + 2.0;
+    double nr = std::max(3.0 * hd + 2.0, op.rmin + hd + 1.0);
     op.near_r2 = nr * nr;
   }
 

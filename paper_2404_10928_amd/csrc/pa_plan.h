@@ -100,9 +100,8 @@ PA_HD inline FpLayout fp_layout(int wpa, int nsub, size_t elem, size_t pix_bytes
   return L;
 }
 
-// forward gather: tiles listed per pass, and the LDS of that list
-constexpr int kGatherChunk = 1024;
-PA_HD inline size_t gather_lds() { return 2 * kGatherChunk * sizeof(int); }
+// forward gather: no dynamic LDS (each wave keeps its tile selection in registers)
+PA_HD inline size_t gather_lds() { return 0; }
 
 struct Plan {
   OpParams op;

@@ -93,6 +93,12 @@ def test_sensors_inside_grid_clamp(pa):
     check_pair(pa, g2, 6, label="on-pixel")
 
 
+def test_large_distance_clamp(pa):
+    # r_min of many pixels: every clamped pair must take the FP64 near path
+    g = ring_geom(n=(64, 64), S=96, K=400, radius=2.5e-3, r_min=8e-4)
+    check_pair(pa, g, 15, label="r_min 8 px")
+
+
 def test_late_arrivals_dropped(pa):
     g = ring_geom(n=(48, 40), S=64, K=200)
     g = g.replace(dt=g.dt * 0.6)   # far edge arrives after the trace ends
