@@ -45,7 +45,7 @@ struct SC32 {
   float KRN;    // -kr
   float KR2N;   // -2 kr
   float KR2;    // kr^2
-  float pad0;   // (far pairs never reach the distance clamp: see the near test)
+  float CMIN;   // rmin^2 - kr^2: the distance clamp in num units (never reached by far pairs)
   int BASE;     // byte offset of sample (kr - t0i) in this sensor's LDS row
   int act;      // 0: sensor contributes nothing to this tile
   float HALF;   // 0.5 (active) or 0 (inactive): weight multiplier
@@ -149,7 +149,7 @@ __device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], 
   double kr = rint(sqrt(ra2));
   if (!active) {  // benign constants: num = |o|^2 + 1 >= 1, a delay of at most |o| + 1, zero weight
     c.E = 1.f; c.DX2 = 0.f; c.DY2 = 0.f; c.DZ2 = 0.f; c.KRN = 0.f; c.KR2N = 0.f; c.KR2 = 0.f;
-    c.pad0 = 0.f; c.BASE = row_elems * esz; c.act = 0; c.HALF = 0.f;
+    c.CMIN = 1.f; c.BASE = row_elems * esz; c.act = 0; c.HALF = 0.f;
     return;
   }
   c.E = (float)(ra2 - kr * kr);
@@ -159,7 +159,7 @@ __device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], 
   c.KRN = (float)(-kr);
   c.KR2N = (float)(-2.0 * kr);
   c.KR2 = (float)(kr * kr);
-  c.pad0 = 0.f;
+  c.CMIN = (float)(P.rmin * P.rmin - kr * kr);
   c.BASE = ((int)kr - P.t0i - klo + row_elems) * esz;
   c.act = 1;
   c.HALF = 0.5f;
@@ -192,13 +192,17 @@ static_assert(sizeof(Near32) == 32, "Near32 layout");
 
 // The per-pair arithmetic.  Returns the LDS byte address of tap k0 (rows of
 // ESZ-byte elements), the fraction f and the tap weight in kernel units
-// (FP32: 1 / (2R); FP64: 1 / R).
-template <int ND, bool FRAC, int ESZ>
+// (FP32: 1 / (2R); FP64: 1 / R).  Far pairs never reach the distance clamp
+// (the near radius covers r_min), so CLAMP only chooses whether the max
+// instruction is emitted: both choices give the same taps, and the kernels
+// use whichever schedules better (measured: A without, A^T with).
+template <int ND, bool FRAC, int ESZ, bool CLAMP = true>
 __device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, int& kbyte, float& f, float& wt) {
   float t = px.q + c.E;
   float num = fmaf(px.oy, c.DY2, t);
   if (ND == 3) num = fmaf(px.oz, c.DZ2, num);
   num = fmaf(px.ox, c.DX2, num);
+  if (CLAMP) num = fmaxf(num, c.CMIN);
   const float R2 = num + c.KR2;
   const float w = __builtin_amdgcn_rsqf(R2);
   const float da = fmaf(R2, w, c.KRN);       // R - kr, FP32 estimate
@@ -232,7 +236,7 @@ __device__ __forceinline__ void phase_near(const Near32& n, const double o[3], d
   kbyte = (int)fl * ESZ + base;
 }
 
-template <int ND, bool FRAC, int ESZ>
+template <int ND, bool FRAC, int ESZ, bool CLAMP = true>
 __device__ __forceinline__ void phase(const SC64& c, const Pix64& px, float, int& kbyte, double& f, double& wt) {
   const double dx = px.ox + c.DX;
   const double dy = px.oy + c.DY;
@@ -634,7 +638,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
       xn = xm[pq];
       int kb;
       T f, wt;
-      phase<ND, FRAC, HB>(c, px, t0f, kb, f, wt);
+      phase<ND, FRAC, HB, false>(c, px, t0f, kb, f, wt);
       H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
       if constexpr (F32) {
         const float vs = (wt * xp) * scl;
