@@ -58,6 +58,9 @@ def _configure(lib):
         lib.or_power_sigma2.restype = ctypes.c_double
         lib.or_tv2d.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, dp]
         lib.or_tv2d.restype = ctypes.c_double
+        lib.or_fista.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 dp, dp, ctypes.c_int]
     return lib
 
 
@@ -165,6 +168,23 @@ def power_sigma2(g, iters=30, threads=None):
     if v < 0:
         raise ValueError("oracle: bad arguments")
     return float(v)
+
+
+def fista(g, y, iters, lam, alpha, beta, eps, omega, nonneg=False, x_history=False, threads=None):
+    """FISTA on ||A x - y||^2 + lam ||x||^2 + beta TV_eps(x) + alpha ||x||_1 from x0 = 0.
+    Returns (x_N, hz, hx): hz[k] = F(z_k) for k < N, hz[N] = F(x_N); hx[k] = F(x_k)
+    (None unless x_history, which costs one more forward per iteration)."""
+    lib = _load()
+    cg, keep = _geom(g)
+    y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1)
+    x = np.zeros(g.image_shape, dtype=np.float64)
+    hz = np.zeros(iters + 1, dtype=np.float64)
+    hx = np.zeros(iters + 1, dtype=np.float64) if x_history else None
+    if lib.or_fista(ctypes.byref(cg), _dp(y), _dp(x), int(iters), float(lam), float(alpha), float(beta),
+                    float(eps), float(omega), 1 if nonneg else 0, _dp(hz),
+                    _dp(hx) if hx is not None else None, _threads(threads)) != 0:
+        raise ValueError("oracle: bad arguments")
+    return x, hz, hx
 
 
 def tv2d(x, eps=1e-8):

@@ -276,3 +276,85 @@ double or_tv2d(const double* x, int32_t nx, int32_t ny, double eps, double* grad
   }
   return tv;
 }
+
+/* Soft threshold: the proximal map of tau * |v| (of tau * v + the indicator
+ * of v >= 0 when nonneg). */
+static double shrink(double v, double tau, int nonneg) {
+  if (nonneg) return v > tau ? v - tau : 0.0;
+  if (v > tau) return v - tau;
+  if (v < -tau) return v + tau;
+  return 0.0;
+}
+
+/* F(x) = ||A x - y||^2 + lambda ||x||^2 + beta TV_eps(x) + alpha ||x||_1,
+ * with the TV term only when beta != 0.  r is scratch of S*K doubles. */
+static double fista_objective(const or_geom* g, const double* y, const double* x, double lambda,
+                              double alpha, double beta, double eps, double* r, int threads) {
+  const int64_t P = npix(g);
+  const int64_t M = (int64_t)g->n_sensors * g->n_samples;
+  or_forward(g, x, r, threads);
+  for (int64_t i = 0; i < M; ++i) r[i] -= y[i];
+  double l1 = 0.0;
+  for (int64_t i = 0; i < P; ++i) l1 += fabs(x[i]);
+  double f = dot(r, r, M) + lambda * dot(x, x, P) + alpha * l1;
+  if (beta != 0.0) f += beta * or_tv2d(x, g->nx, g->ny, eps, NULL);
+  return f;
+}
+
+/* Accelerated proximal gradient (FISTA, Beck and Teboulle 2009) on the
+ * objective of Eq. 8 with the sparsifying transforms taken as the identity,
+ * plus a Tikhonov term:
+ *   F(x) = ||A x - y||^2 + lambda ||x||^2 + beta TV_eps(x) + alpha ||x||_1.
+ * The first three terms are smooth; half their gradient is
+ *   G(z) = A^T (A z - y) + lambda z + (beta / 2) dTV_eps/dz.
+ * From x_0 = z_0 = 0 and t_0 = 1, for k = 0 .. iters - 1:
+ *   x_{k+1} = shrink(z_k - omega G(z_k), omega alpha / 2)
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+ *   z_{k+1} = x_{k+1} + ((t_k - 1) / t_{k+1}) (x_{k+1} - x_k)
+ * (shrink keeps x >= 0 as well when nonneg).  omega is the step, 1 / L for
+ * L = sigma2 + lambda + 4 beta / eps the Lipschitz constant of G.
+ * hz (may be NULL): [iters + 1], hz[k] = F(z_k) for k < iters, hz[iters] = F(x_iters).
+ * hx (may be NULL): [iters + 1], hx[k] = F(x_k).
+ * The TV term needs a 2D image (ndim 2); returns -1 otherwise when beta != 0. */
+int or_fista(const or_geom* g, const double* y, double* x, int iters, double lambda, double alpha,
+             double beta, double eps, double omega, int nonneg, double* hz, double* hx, int threads) {
+  if (!geom_ok(g) || iters < 0 || !(lambda >= 0) || !(alpha >= 0) || !(beta >= 0) || !(omega > 0)) return -1;
+  if (beta != 0.0 && (g->ndim != 2 || !(eps > 0))) return -1;
+  const int64_t P = npix(g);
+  const int64_t M = (int64_t)g->n_sensors * g->n_samples;
+  double* r = (double*)malloc(sizeof(double) * (M ? M : 1));
+  double* z = (double*)malloc(sizeof(double) * (P ? P : 1));
+  double* grad = (double*)malloc(sizeof(double) * (P ? P : 1));
+  double* tvg = (double*)malloc(sizeof(double) * (P ? P : 1));
+  double* xn = (double*)malloc(sizeof(double) * (P ? P : 1));
+  if (!r || !z || !grad || !tvg || !xn) { free(r); free(z); free(grad); free(tvg); free(xn); return -1; }
+  memset(x, 0, sizeof(double) * P);
+  memset(z, 0, sizeof(double) * P);
+  double t = 1.0;
+  const double tau = omega * alpha / 2.0;
+  if (hx) hx[0] = fista_objective(g, y, x, lambda, alpha, beta, eps, r, threads);
+  for (int k = 0; k < iters; ++k) {
+    if (hz) hz[k] = fista_objective(g, y, z, lambda, alpha, beta, eps, r, threads);
+    /* G(z) */
+    or_forward(g, z, r, threads);
+    for (int64_t i = 0; i < M; ++i) r[i] -= y[i];
+    or_adjoint(g, r, grad, threads);
+    for (int64_t i = 0; i < P; ++i) grad[i] += lambda * z[i];
+    if (beta != 0.0) {
+      or_tv2d(z, g->nx, g->ny, eps, tvg);
+      for (int64_t i = 0; i < P; ++i) grad[i] += 0.5 * beta * tvg[i];
+    }
+    for (int64_t i = 0; i < P; ++i) xn[i] = shrink(z[i] - omega * grad[i], tau, nonneg);
+    const double t1 = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const double mu = (t - 1.0) / t1;
+    for (int64_t i = 0; i < P; ++i) {
+      z[i] = xn[i] + mu * (xn[i] - x[i]);
+      x[i] = xn[i];
+    }
+    t = t1;
+    if (hx) hx[k + 1] = fista_objective(g, y, x, lambda, alpha, beta, eps, r, threads);
+  }
+  if (hz) hz[iters] = hx ? hx[iters] : fista_objective(g, y, x, lambda, alpha, beta, eps, r, threads);
+  free(r); free(z); free(grad); free(tvg); free(xn);
+  return 0;
+}

@@ -63,6 +63,13 @@ double or_power_sigma2(const or_geom* g, int iters, int threads);
  * grad is not NULL, writes dTV/dx. */
 double or_tv2d(const double* x, int32_t nx, int32_t ny, double eps, double* grad);
 
+/* FISTA on F(x) = ||A x - y||^2 + lambda ||x||^2 + beta TV_eps(x) + alpha ||x||_1
+ * (the objective of Eq. 8 with identity transforms), x0 = 0, fixed step omega;
+ * nonneg adds the constraint x >= 0.  hz[k] = F(z_k) (k < iters), hz[iters] =
+ * F(x_iters); hx[k] = F(x_k); either may be NULL.  TV needs ndim 2.  Returns 0 / -1. */
+int or_fista(const or_geom* g, const double* y, double* x, int iters, double lambda, double alpha,
+             double beta, double eps, double omega, int nonneg, double* hz, double* hx, int threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,13 @@ MUTANTS = {
     "tv_gradient_lost_term": ("          grad[p] -= dy / m;\n", ""),
     "tv_vertical_difference": ("const double dy = iy + 1 < ny ? x[p + nx] - x[p] : 0.0;",
                                "const double dy = iy + 1 < ny ? x[p + 1] - x[p] : 0.0;"),
+    "fista_no_momentum": ("const double mu = (t - 1.0) / t1;", "const double mu = 0.0 * (t - 1.0) / t1;"),
+    "fista_momentum_reversed": ("z[i] = xn[i] + mu * (xn[i] - x[i]);", "z[i] = xn[i] + mu * (x[i] - xn[i]);"),
+    "fista_full_threshold": ("const double tau = omega * alpha / 2.0;", "const double tau = omega * alpha;"),
+    "fista_full_tv_weight": ("grad[i] += 0.5 * beta * tvg[i];", "grad[i] += beta * tvg[i];"),
+    "fista_lambda_dropped": ("grad[i] += lambda * z[i];", "grad[i] += 0.0 * z[i];"),
+    "fista_nonneg_ignores_threshold": ("if (nonneg) return v > tau ? v - tau : 0.0;",
+                                       "if (nonneg) return v > 0.0 ? v : 0.0;"),
 }
 
 PINS = [
@@ -45,6 +52,10 @@ PINS = [
     pins.test_landweber_closed_form,
     pins.test_tv_closed_forms,
     pins.test_tv_gradient_matches_finite_differences_and_shift_invariance,
+    lambda: pins.test_fista_without_penalties_reaches_normal_equations(False),
+    lambda: pins.test_fista_l1_satisfies_kkt(True),
+    pins.test_fista_tv_satisfies_kkt,
+    pins.test_fista_meets_the_accelerated_rate_bound,
 ]
 
 

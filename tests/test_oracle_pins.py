@@ -342,3 +342,118 @@ def test_loss_gradient_is_exact_for_the_quadratic_term():
         fp = oracle.loss_gradient(g, x + e, y, 1e-3, 1e-2)[0]
         fm = oracle.loss_gradient(g, x - e, y, 1e-3, 1e-2)[0]
         assert grad_t.reshape(-1)[p] == pytest.approx((fp - fm) / (2 * h), rel=1e-5, abs=1e-6 * np.abs(grad_t).max())
+
+
+# --------------------------------------------------------------------------
+# FISTA on the l1 + TV objective of Eq. 8 (identity sparsifying transforms)
+
+def fista_objective_dense(A, y, x, lam, alpha, beta, eps, shape):
+    r = A @ x - y
+    F = r @ r + lam * x @ x + alpha * np.abs(x).sum()
+    if beta:
+        F += beta * oracle.tv2d(x.reshape(shape), eps)[0]
+    return F
+
+
+def tv_gradient_fd(x, eps, shape, h=1e-7):
+    """dTV/dx by central differences of the TV value alone."""
+    g = np.zeros(x.size)
+    for p in range(x.size):
+        e = np.zeros(x.size)
+        e[p] = h
+        g[p] = (oracle.tv2d((x + e).reshape(shape), eps)[0] - oracle.tv2d((x - e).reshape(shape), eps)[0]) / (2 * h)
+    return g
+
+
+def fista_setup(seed, lam_rel=1e-3):
+    g, y = tiny_problem(seed)
+    A = dense(g)
+    L2 = np.linalg.norm(A, 2) ** 2
+    return g, y, A, L2, lam_rel * L2
+
+
+@pytest.mark.parametrize("nonneg", [False, True])
+def test_fista_without_penalties_reaches_normal_equations(nonneg):
+    """alpha = beta = 0: the minimiser is (A^T A + lam I)^-1 A^T y (numpy solve);
+    with the x >= 0 constraint it must satisfy the bound-constrained KKT conditions."""
+    g, y, A, L2, lam = fista_setup(11, 1e-1)
+    omega = 1.0 / (L2 + lam)
+    x, hz, _ = oracle.fista(g, y, 400, lam, 0.0, 0.0, 1.0, omega, nonneg=nonneg)
+    x = x.reshape(-1)
+    b = A.T @ y.reshape(-1)
+    if not nonneg:
+        x_ref = np.linalg.solve(A.T @ A + lam * np.eye(A.shape[1]), b)
+        np.testing.assert_allclose(x, x_ref, rtol=1e-9, atol=1e-9 * np.abs(x_ref).max())
+    else:
+        grad = 2 * (A.T @ (A @ x) - b + lam * x)
+        scale = np.abs(2 * b).max()
+        assert np.all(x >= 0)
+        assert np.all(np.abs(grad[x > 0]) <= 1e-8 * scale)
+        assert np.all(grad[x == 0] >= -1e-8 * scale)
+    assert hz[-1] == pytest.approx(fista_objective_dense(A, y.reshape(-1), x, lam, 0, 0, 1, g.image_shape), rel=1e-12)
+
+
+@pytest.mark.parametrize("nonneg", [False, True])
+def test_fista_l1_satisfies_kkt(nonneg):
+    """beta = 0, alpha > 0 (lasso with a ridge term): at the minimiser,
+    2(A^T(Ax - y) + lam x)_i = -alpha sign(x_i) where x_i != 0 and
+    |2(A^T(Ax - y) + lam x)_i| <= alpha where x_i = 0 (>= -alpha with x >= 0)."""
+    g, y, A, L2, lam = fista_setup(12, 1e-2)
+    b = A.T @ y.reshape(-1)
+    alpha = 0.3 * np.abs(2 * b).max()
+    omega = 1.0 / (L2 + lam)
+    x, hz, hx = oracle.fista(g, y, 1500, lam, alpha, 0.0, 1.0, omega, nonneg=nonneg, x_history=True)
+    x = x.reshape(-1)
+    grad = 2 * (A.T @ (A @ x) - b + lam * x)
+    nz = x != 0
+    assert 0 < nz.sum() < x.size        # the threshold is active on some pixels and not on others
+    np.testing.assert_allclose(grad[nz], -alpha * np.sign(x[nz]), rtol=0, atol=1e-7 * alpha)
+    if nonneg:
+        assert np.all(x >= 0) and np.all(grad[~nz] >= -alpha * (1 + 1e-7))
+    else:
+        assert np.all(np.abs(grad[~nz]) <= alpha * (1 + 1e-7))
+    assert hx[-1] == pytest.approx(fista_objective_dense(A, y.reshape(-1), x, lam, alpha, 0, 1, g.image_shape),
+                                   rel=1e-12)
+
+
+def test_fista_tv_satisfies_kkt():
+    """beta > 0 with alpha > 0 and x >= 0: stationarity with the TV gradient
+    taken by central differences of the TV value (not the oracle's analytic
+    gradient)."""
+    g, y, A, L2, lam = fista_setup(13, 1e-3)
+    b = A.T @ y.reshape(-1)
+    eps = 0.05
+    beta = 0.05 * np.abs(2 * b).max()
+    alpha = 0.6 * np.abs(2 * b).max()
+    omega = 1.0 / (L2 + lam + 4 * beta / eps)
+    x, hz, hx = oracle.fista(g, y, 3000, lam, alpha, beta, eps, omega, nonneg=True, x_history=True)
+    x = x.reshape(-1)
+    grad = 2 * (A.T @ (A @ x) - b + lam * x) + beta * tv_gradient_fd(x, eps, g.image_shape)
+    nz = x > 0
+    assert 0 < nz.sum() < x.size
+    np.testing.assert_allclose(grad[nz], -alpha, rtol=0, atol=1e-6 * alpha)
+    assert np.all(grad[~nz] >= -alpha * (1 + 1e-6))
+    assert hx[-1] == pytest.approx(fista_objective_dense(A, y.reshape(-1), x, lam, alpha, beta, eps, g.image_shape),
+                                   rel=1e-12)
+
+
+def test_fista_meets_the_accelerated_rate_bound():
+    """Beck and Teboulle's bound F(x_k) - F* <= 2 L ||x_0 - x*||^2 / (k + 1)^2,
+    with L = 2 / omega the Lipschitz constant of the smooth part's gradient.  The
+    data are A v for the eigenvector v of A^T A whose eigenvalue is about
+    L / (4 N): an unaccelerated proximal gradient leaves an error near
+    (1 - 1/(2N))^(2k) there, an order of magnitude above the bound at k = N."""
+    g, _, A, L2, lam = fista_setup(14, 1e-9)
+    w, V = np.linalg.eigh(A.T @ A)
+    N = 300
+    omega = 1.0 / (L2 + lam)
+    j = int(np.argmin(np.abs(w * omega - 1.0 / (2 * N))))
+    y = (A @ V[:, j]).reshape(g.data_shape)
+    alpha = 1e-4 * np.abs(2 * A.T @ y.reshape(-1)).max()
+    xs, _, _ = oracle.fista(g, y, 40000, lam, alpha, 0.0, 1.0, omega)
+    Fs = fista_objective_dense(A, y.reshape(-1), xs.reshape(-1), lam, alpha, 0, 1, g.image_shape)
+    _, _, hx = oracle.fista(g, y, N, lam, alpha, 0.0, 1.0, omega, x_history=True)
+    k = np.arange(1, N + 1)
+    bound = 2 * (2 / omega) * np.sum(xs ** 2) / (k + 1) ** 2
+    assert np.all(hx[1:] - Fs <= bound)
+    assert np.all(hx >= Fs * (1 - 1e-12))
