@@ -232,6 +232,8 @@ def main():
         out["batched_frames"] = batched_leg(pa, torch, dev, tune=not args.no_tune)
         out["volume_3d"] = volume_leg(pa, torch, dev, tune=not args.no_tune)
         out["landweber"] = landweber_leg(pa, torch, dev, geom, y, w)
+        out["fista_l1_tv"] = fista_leg(pa, torch, dev, geom, y, w)
+        out["dense_matrix"] = dense_leg(pa, torch, dev)
         out["differentiable"] = autograd_leg(pa, torch, dev)
 
     print(json.dumps(out))
@@ -301,6 +303,74 @@ def landweber_leg(pa, torch, dev, geom, y, w):
     return {"workload": f"512x512 ring workload, {w.iters} Landweber steps + 30 power-iteration steps, FP32",
             "ms_per_solve": t * 1e3, "solves_per_s": 1.0 / t, "sigma2": s2, "omega": om,
             "F_first": float(sv.history[0]), "F_last": float(sv.history[-1])}
+
+
+def fista_leg(pa, torch, dev, geom, y, w):
+    """The l1 + TV objective of Eq. 8 on the 512x512 workload: 50 FISTA steps
+    with the step from 30 power-iteration steps, x >= 0, FP32, one graph replay
+    per solve.  Weights from the data: alpha = 1e-2 max|2 A^T y|,
+    beta = 1e-4 max|2 A^T y|, eps = 1e-2."""
+    b = float(pa.adjoint(y, geom).abs().max()) * 2.0
+    alpha, beta, eps = 1e-2 * b, 1e-4 * b, 1e-2
+    sv = pa.FistaSolver(geom, torch.float32, w.iters, w.lam, alpha, beta, eps, omega=0.0, power_iters=30,
+                        nonneg=True, graph=True, device=dev)
+    x = torch.empty(geom.image_shape, dtype=torch.float32, device=dev)
+    sv.solve(y, x)
+    t = _sync_time(torch, lambda: sv.solve(y, x), 3)
+    om, s2 = sv.step()
+    return {"workload": f"512x512 ring workload, {w.iters} FISTA steps + 30 power-iteration steps, "
+                        f"l1 + TV (alpha {alpha:.3e}, beta {beta:.3e}, eps {eps}), x >= 0, FP32",
+            "ms_per_solve": t * 1e3, "solves_per_s": 1.0 / t, "sigma2": s2, "omega": om,
+            "F_first": float(sv.history[0]), "F_last": float(sv.history[-1]),
+            "zero_fraction": float((x == 0).double().mean())}
+
+
+def dense_leg(pa, torch, dev):
+    """The paper's own formulation on the 128x128 workload: the dense FP64
+    matrix (128 sensors x 512 samples by 16384 pixels, 8.6 GB) built on the
+    GPU and applied as y = A x and x = A^T y, each reading the whole matrix
+    from HBM; next to the matrix-free FP64 operators on the same geometry."""
+    from synth import make_config
+    w = make_config("C1")
+    g = pa.DeviceGeometry(w.geom, dev)
+    D = pa.DenseMatrix(g, torch.float64, dev)
+    x = torch.from_numpy(w.x).to(dev)
+    yv = torch.randn(g.data_shape, dtype=torch.float64, device=dev)
+    yo = torch.empty_like(yv)
+    xo = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+
+    def ev(fn, reps):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_f = ev(lambda: D.forward(x, yo), 10)
+    t_a = ev(lambda: D.adjoint(yv, xo), 10)
+    op = pa.Operator(g, torch.float64, dev)
+    t_mf = ev(lambda: op.forward_(x, yo), 50)
+    t_ma = ev(lambda: op.adjoint_(yv, xo), 50)
+    nbytes = D.matrix.numel()
+    out = {"workload": "128x128 image, 128 sensors, 512 samples, dense FP64 matrix (the paper's kn layout: "
+                       f"{g.n_sensors * g.n_samples} x {g.n_pixels})",
+           "matrix_bytes": nbytes,
+           "us_per_apply": {"dense A": t_f * 1e6, "dense A^T": t_a * 1e6,
+                            "matrix-free A (FP64)": t_mf * 1e6, "matrix-free A^T (FP64)": t_ma * 1e6},
+           "roofline": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0,
+                        "achieved_A": nbytes / t_f / 1e9, "achieved_AT": nbytes / t_a / 1e9,
+                        "frac_A": nbytes / t_f / 8e12, "frac_AT": nbytes / t_a / 8e12,
+                        "bytes_per_launch": "the matrix once (x, y and the A^T partials are < 1 %)"}}
+    del D
+    torch.cuda.empty_cache()
+    print(f"[bench] dense 128^2 FP64: A {t_f * 1e6:.0f} us ({nbytes / t_f / 1e9:.0f} GB/s), "
+          f"A^T {t_a * 1e6:.0f} us; matrix-free {t_mf * 1e6:.1f} / {t_ma * 1e6:.1f} us", file=sys.stderr, flush=True)
+    return out
 
 
 def autograd_leg(pa, torch, dev):

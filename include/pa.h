@@ -79,6 +79,7 @@ typedef struct {
 /* Flags for pa_cgls_solve. */
 #define PA_X0_ZERO 1u   /* start from x0 = 0 and ignore the contents of x on entry */
 #define PA_USE_GRAPH 2u /* enqueue the whole solve as one HIP graph (captured once per argument set, then replayed) */
+#define PA_NONNEG 4u    /* pa_fista_solve only: constrain the image to x >= 0 */
 
 /* Host-only check of a geometry: sizes, finiteness, and that the kernels can
  * tile it.  Touches no GPU state and dereferences no device pointer. */
@@ -142,6 +143,66 @@ pa_status pa_landweber_solve(const pa_geometry* g, pa_dtype dtype, const void* y
 /* After synchronising: the step the last solve on this workspace used, and
  * the eigenvalue estimate (0 when the step was given).  One blocking copy. */
 pa_status pa_landweber_step(const void* workspace, double* omega, double* sigma2);
+
+/* ------------------------------------------ sparsity-regularised objective
+ * The compressed-sensing objective of Eq. 8 with both sparsifying transforms
+ * taken as the identity, plus the Tikhonov term of the solvers above:
+ *   F(x) = ||A x - y||^2 + lambda ||x||^2 + beta TV_eps(x) + alpha ||x||_1
+ * TV_eps(x) = sum_p sqrt(dx_p^2 + dy_p^2 + eps^2) over forward differences of
+ * the 2D image (zero past the last column and row): the smoothed isotropic
+ * form of the TV penalty, whose gradient is the reweighted difference-matrix
+ * term t2 of Table 3 with the weights applied per pixel.
+ * Solved by the accelerated proximal gradient method (FISTA, Beck and
+ * Teboulle 2009) from x_0 = z_0 = 0, t_0 = 1, for k = 0 .. iters-1:
+ *   x_{k+1} = shrink(z_k + omega (A^T (y - A z_k) - lambda z_k - (beta/2) dTV(z_k)), omega alpha / 2)
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+ *   z_{k+1} = x_{k+1} + ((t_k - 1) / t_{k+1}) (x_{k+1} - x_k)
+ * shrink(v, tau) = sign(v) max(|v| - tau, 0), or max(v - tau, 0) with
+ * PA_NONNEG.  With omega > 0 the caller's step is used; with omega == 0 it is
+ * 1 / (sigma2 + lambda + 4 beta / eps), sigma2 from power_iters
+ * power-iteration steps as in pa_landweber_solve (the inverse Lipschitz
+ * constant of the smooth part's half-gradient).
+ * alpha, beta, lambda >= 0 and finite; beta > 0 needs eps > 0 and a 2D image
+ * (PA_ERR_UNSUPPORTED otherwise); eps is ignored when beta == 0.
+ * The solve always starts from 0: x is output only.  Flags: PA_NONNEG,
+ * PA_USE_GRAPH.  history: device double [iters + 1] with F(z_k) for
+ * k < iters (the objective at the point where the gradient is taken) and
+ * F(x_iters) last, or NULL.  Vectors are FP32 under PA_F32 and FP64 under
+ * PA_F64; every norm, TV sum and scalar is FP64 on the GPU.  Workspace rules
+ * and errors as for pa_cgls_solve; pa_fista_step reads the step used. */
+size_t pa_fista_workspace_bytes(const pa_geometry* g, pa_dtype dtype);
+pa_status pa_fista_solve(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, int32_t iters, double lambda,
+                         double alpha, double beta, double eps, double omega, int32_t power_iters, uint32_t flags,
+                         void* workspace, size_t workspace_bytes, double* history, void* hip_stream);
+
+/* After synchronising: the step the last FISTA solve on this workspace used
+ * and the eigenvalue estimate (0 when the step was given).  One blocking copy. */
+pa_status pa_fista_step(const void* workspace, double* omega, double* sigma2);
+
+/* ------------------------------------------------------ dense matrix path
+ * The paper's own formulation (Experiment 2): the time-domain measurement
+ * matrix kn materialised densely and applied as kn * x and kn' * y (the
+ * statement that takes 96.7 % of Table 3).  The entries are those of
+ * pa_forward: A[m][p] = (1/R_ps) max(0, 1 - |k - tau_ps|) for m = s * K + k,
+ * formed in FP64 and rounded once to the dtype.  Rows are ld = P rounded up
+ * to a multiple of 32 apart (padding columns are zero), so the matrix takes
+ * pa_dense_matrix_bytes() = S * K * ld * sizeof(element) bytes of device
+ * memory, owned by the caller (8.6 GB in FP64 for a 128 x 128 image, 128
+ * sensors and 512 samples).  Both products accumulate in FP64 in a fixed
+ * order and are bound by HBM bandwidth: each reads the whole matrix.
+ * Returns 0 from the size queries when the arguments are invalid or the
+ * matrix would exceed 2^40 bytes. */
+size_t pa_dense_matrix_bytes(const pa_geometry* g, pa_dtype dtype);
+/* A := the dense matrix of g (device, >= pa_dense_matrix_bytes(), 16-byte aligned). */
+pa_status pa_dense_build(const pa_geometry* g, pa_dtype dtype, void* matrix, size_t matrix_bytes, void* hip_stream);
+/* y := A x with a matrix pa_dense_build wrote for the same geometry and dtype. */
+pa_status pa_dense_forward(const pa_geometry* g, pa_dtype dtype, const void* matrix, size_t matrix_bytes,
+                           const void* x, void* y, void* hip_stream);
+/* x := A^T y; workspace (device, caller-owned, 256-byte aligned) holds the FP64
+ * partial sums of row chunks. */
+size_t pa_dense_adjoint_workspace_bytes(const pa_geometry* g, pa_dtype dtype);
+pa_status pa_dense_adjoint(const pa_geometry* g, pa_dtype dtype, const void* matrix, size_t matrix_bytes,
+                           const void* y, void* x, void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /* ------------------------------------------------------------------ batches
  * Many frames of uneven image size, sensor count and trace length, each with

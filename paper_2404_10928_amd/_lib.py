@@ -27,13 +27,16 @@ PA_F32 = 0
 PA_F64 = 1
 PA_X0_ZERO = 1
 PA_USE_GRAPH = 2
+PA_NONNEG = 4
 
 EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspace_bytes", "pa_cgls_solve",
            "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version", "pa_batch_create", "pa_batch_destroy",
            "pa_batch_offsets", "pa_batch_workspace_bytes", "pa_batch_cgls_workspace_bytes", "pa_batch_forward",
            "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations", "pa_autotune", "pa_tuning_clear",
            "pa_landweber_workspace_bytes", "pa_landweber_solve", "pa_landweber_step",
-           "pa_batch_autotune_workspace_bytes", "pa_batch_autotune"]
+           "pa_batch_autotune_workspace_bytes", "pa_batch_autotune", "pa_fista_workspace_bytes", "pa_fista_solve",
+           "pa_fista_step", "pa_dense_matrix_bytes", "pa_dense_build", "pa_dense_forward",
+           "pa_dense_adjoint_workspace_bytes", "pa_dense_adjoint"]
 
 
 class PaTuning(ctypes.Structure):
@@ -118,6 +121,24 @@ def load(path: str = LIB_PATH):
     lib.pa_batch_autotune_workspace_bytes.restype = ctypes.c_size_t
     lib.pa_batch_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_int32)]
     lib.pa_batch_autotune.restype = ctypes.c_int
+    lib.pa_fista_workspace_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_fista_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_fista_solve.argtypes = [gp, ctypes.c_int, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
+                                   vp, ctypes.c_size_t, vp, vp]
+    lib.pa_fista_solve.restype = ctypes.c_int
+    lib.pa_fista_step.argtypes = [vp, dpp, dpp]
+    lib.pa_fista_step.restype = ctypes.c_int
+    lib.pa_dense_matrix_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_dense_matrix_bytes.restype = ctypes.c_size_t
+    lib.pa_dense_adjoint_workspace_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_dense_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_dense_build.argtypes = [gp, ctypes.c_int, vp, ctypes.c_size_t, vp]
+    lib.pa_dense_build.restype = ctypes.c_int
+    lib.pa_dense_forward.argtypes = [gp, ctypes.c_int, vp, ctypes.c_size_t, vp, vp, vp]
+    lib.pa_dense_forward.restype = ctypes.c_int
+    lib.pa_dense_adjoint.argtypes = [gp, ctypes.c_int, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pa_dense_adjoint.restype = ctypes.c_int
     _lib = lib
     return lib
 

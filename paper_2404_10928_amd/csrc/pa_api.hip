@@ -15,6 +15,7 @@
 #include <new>
 
 #include "pa.h"
+#include "pa_dense.h"
 #include "pa_kernels.h"
 #include "pa_plan.h"
 
@@ -203,6 +204,98 @@ hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
   return pa::launch_lw_final(part_r, L.g_m, part_n, L.g_p, S.lambda, S.hist, S.iters, st);
 }
 
+// ------------------------------------------ proximal gradient (FISTA) enqueue
+
+struct FiSolve {
+  const pa::Plan* pl;
+  pa::FistaLayout F;
+  int nx, ny;
+  const void* y;
+  void* x;
+  int iters;
+  double lambda, alpha, beta, eps;
+  double omega;      // > 0: given; 0: estimated by power iteration
+  int power_iters;
+  uint32_t flags;
+  unsigned char* ws;
+  double* hist;
+};
+
+hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
+  const pa::Plan& pl = *S.pl;
+  const pa::LwLayout& L = S.F.lw;
+  const pa_dtype dt = pl.dtype;
+  unsigned char* ws = S.ws;
+  int* status = reinterpret_cast<int*>(ws + L.status);
+  double* alpha0 = reinterpret_cast<double*>(ws + L.alpha0);
+  double* sigma2 = reinterpret_cast<double*>(ws + L.sigma2);
+  double* omega = reinterpret_cast<double*>(ws + L.omega);
+  double* part_r = reinterpret_cast<double*>(ws + L.part_r);
+  double* part_s = reinterpret_cast<double*>(ws + L.part_s);
+  double* part_x = reinterpret_cast<double*>(ws + L.part_x);
+  double* part_n = reinterpret_cast<double*>(ws + L.part_n);
+  double* part_tv = reinterpret_cast<double*>(ws + S.F.part_tv);
+  double* part_l1 = reinterpret_cast<double*>(ws + S.F.part_l1);
+  void* r = ws + L.vec_r;
+  void* q = ws + L.vec_q;
+  void* s = ws + L.vec_s;
+  void* v = ws + L.vec_v;
+  void* zb[2] = {ws + S.F.vec_z0, ws + S.F.vec_z1};
+  void* fwd = ws + L.fwd;
+  const int nonneg = (S.flags & PA_NONNEG) ? 1 : 0;
+  hipError_t e;
+  // step: 1 / (sigma2 + lambda + 4 beta / eps), the inverse Lipschitz constant
+  // of the smooth part's half-gradient (8 / eps bounds the TV Hessian)
+  if ((e = pa::launch_fill(PA_F64, sigma2, 1, st)) != hipSuccess) return e;
+  if (!(S.omega > 0.0) && pl.P > 0) {
+    if ((e = pa::launch_fill_value(dt, v, pl.P, 1.0 / std::sqrt((double)pl.P), st)) != hipSuccess) return e;
+    for (int it = 0; it < S.power_iters; ++it) {
+      if ((e = pa::launch_forward(pl, v, q, fwd, nullptr, st)) != hipSuccess) return e;
+      if (pl.bp_grid > 0 && (e = pa::launch_adjoint(pl, q, s, nullptr, st)) != hipSuccess) return e;
+      if ((e = pa::launch_norm2(dt, s, pl.P, part_n, st)) != hipSuccess) return e;
+      if ((e = pa::launch_pw_scale(dt, v, s, pl.P, part_n, sigma2, st)) != hipSuccess) return e;
+    }
+  }
+  const double tv_l = S.beta > 0.0 ? 4.0 * S.beta / S.eps : 0.0;
+  if ((e = pa::launch_pw_omega(sigma2, S.lambda + tv_l, S.omega, omega, st)) != hipSuccess) return e;
+  if ((e = pa::launch_fill(dt, S.x, pl.P, st)) != hipSuccess) return e;
+  if ((e = pa::launch_fill(dt, zb[0], pl.P, st)) != hipSuccess) return e;
+  const int gbp = std::max(pl.bp_grid, 1);
+  double t = 1.0;
+  for (int k = 0; k < S.iters; ++k) {
+    void* z = zb[k & 1];
+    void* zn = zb[(k + 1) & 1];
+    // r = y - A z ; s = A^T r - lambda z with the partials of ||z||^2 (the
+    // epilogue's step is the zero that init_r writes, so z is unchanged)
+    if ((e = pa::launch_forward(pl, z, q, fwd, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
+    if (pl.bp_grid == 0) {
+      if ((e = pa::launch_fill(PA_F64, part_s, gbp, st)) != hipSuccess) return e;
+      if ((e = pa::launch_fill(PA_F64, part_x, gbp, st)) != hipSuccess) return e;
+    } else {
+      pa::CgArgs cg{z, z, alpha0, S.lambda, part_s, part_x};
+      if ((e = pa::launch_adjoint(pl, r, s, &cg, st)) != hipSuccess) return e;
+    }
+    const double t1 = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const double mu = (t - 1.0) / t1;
+    if ((e = pa::launch_fista_step(dt, z, s, S.x, zn, S.nx, S.ny, pl.P, S.beta, S.eps, S.alpha, omega, mu, nonneg,
+                                   part_tv, part_l1, st)) != hipSuccess)
+      return e;
+    if ((e = pa::launch_fista_hist(part_r, L.g_m, part_x, gbp, part_tv, part_l1, L.g_p, S.lambda, S.beta, S.alpha,
+                                   S.hist, k, st)) != hipSuccess)
+      return e;
+    t = t1;
+  }
+  // the objective at the final iterate
+  if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
+  if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
+  if ((e = pa::launch_fista_terms(dt, S.x, S.nx, S.ny, pl.P, S.beta, S.eps, part_n, part_tv, part_l1, st)) !=
+      hipSuccess)
+    return e;
+  return pa::launch_fista_hist(part_r, L.g_m, part_n, L.g_p, part_tv, part_l1, L.g_p, S.lambda, S.beta, S.alpha,
+                               S.hist, S.iters, st);
+}
+
 // ------------------------------------------------------------ graph cache
 
 struct GraphKey {
@@ -217,9 +310,10 @@ struct GraphKey {
   void* ws;
   double* hist;
   int device;
-  int kind;           // 0 CGLS, 1 Landweber
-  double omega;       // Landweber: given step (0: estimated)
-  int power_iters;    // Landweber: power-iteration steps
+  int kind;           // 0 CGLS, 1 Landweber, 2 FISTA
+  double omega;       // Landweber, FISTA: given step (0: estimated)
+  int power_iters;    // Landweber, FISTA: power-iteration steps
+  double alpha, beta, eps;  // FISTA: l1 weight, TV weight, TV smoothing
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
@@ -987,6 +1081,180 @@ pa_status pa_landweber_step(const void* workspace, double* omega, double* sigma2
          "read Landweber step");
   if (sigma2) *sigma2 = v[1];
   if (omega) *omega = v[2];
+  return PA_OK;
+}
+
+size_t pa_fista_workspace_bytes(const pa_geometry* g, pa_dtype dtype) {
+  g_err.clear();
+  pa::Plan pl;
+  if (plan_or_fail(g, dtype, &pl) != PA_OK) return 0;
+  return pa::fista_layout(pl).total;
+}
+
+pa_status pa_fista_solve(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, int32_t iters, double lambda,
+                         double alpha, double beta, double eps, double omega, int32_t power_iters, uint32_t flags,
+                         void* workspace, size_t workspace_bytes, double* history, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = plan_or_fail(g, dtype, &pl);
+  if (st != PA_OK) return st;
+  if (iters < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "iters must be >= 0");
+  if (iters > (1 << 20) || power_iters > (1 << 20)) return set_err(PA_ERR_UNSUPPORTED, "iteration count above 2^20");
+  if (!std::isfinite(lambda) || lambda < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "lambda must be finite and >= 0");
+  if (!std::isfinite(alpha) || alpha < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "alpha must be finite and >= 0");
+  if (!std::isfinite(beta) || beta < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "beta must be finite and >= 0");
+  if (beta > 0) {
+    if (!std::isfinite(eps) || !(eps > 0)) return set_err(PA_ERR_INVALID_ARGUMENT, "eps must be finite and > 0");
+    if (g->ndim != 2 || g->nz != 1) return set_err(PA_ERR_UNSUPPORTED, "the TV term (beta > 0) needs a 2D image");
+  }
+  if (!std::isfinite(omega) || omega < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "omega must be finite and >= 0");
+  if (omega == 0.0 && power_iters < 1)
+    return set_err(PA_ERR_INVALID_ARGUMENT, "omega == 0 needs power_iters >= 1 to estimate the step");
+  if (flags & ~(PA_NONNEG | PA_USE_GRAPH)) return set_err(PA_ERR_INVALID_ARGUMENT, "unknown flag bits");
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if (history && !aligned(history, 8)) return set_err(PA_ERR_INVALID_ARGUMENT, "history is not 8-byte aligned");
+  const pa::FistaLayout F = pa::fista_layout(pl);
+  if (!workspace) return set_err(PA_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (workspace_bytes < F.total) return set_err(PA_ERR_WORKSPACE, "workspace smaller than pa_fista_workspace_bytes()");
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  if (overlap(workspace, F.total, x, pl.P * pl.elem) || overlap(workspace, F.total, y, pl.M * pl.elem))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "workspace overlaps x or y");
+  const size_t hb = sizeof(double) * (size_t)(iters + 1);
+  if (history && (overlap(history, hb, workspace, F.total) || overlap(history, hb, x, pl.P * pl.elem) ||
+                  overlap(history, hb, y, pl.M * pl.elem)))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "history overlaps another buffer");
+  FiSolve S{&pl, F, g->nx, g->ny, y, x, iters, lambda, alpha, beta, beta > 0 ? eps : 1.0,
+            omega, omega > 0.0 ? 0 : power_iters, flags, static_cast<unsigned char*>(workspace), history};
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  bool use_graph = (flags & PA_USE_GRAPH) != 0;
+  if (use_graph && s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    PA_HIP(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) use_graph = false;
+  }
+  if (!use_graph) {
+    PA_HIP(enqueue_fista(S, s), "FISTA enqueue");
+    return PA_OK;
+  }
+  GraphKey key;
+  std::memset(&key, 0, sizeof(key));
+  key.g = *g;
+  key.dt = dtype;
+  key.y = y;
+  key.x = x;
+  key.iters = iters;
+  key.lambda = lambda;
+  key.flags = flags;
+  key.ws = workspace;
+  key.hist = history;
+  key.kind = 2;
+  key.omega = omega;
+  key.power_iters = S.power_iters;
+  key.alpha = alpha;
+  key.beta = beta;
+  key.eps = S.eps;
+  PA_HIP(hipGetDevice(&key.device), "hipGetDevice");
+  hipGraphExec_t exec = nullptr;
+  PA_HIP(get_graph(key, [&](hipStream_t cs) { return enqueue_fista(S, cs); }, &exec), "FISTA graph capture");
+  PA_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
+  return PA_OK;
+}
+
+pa_status pa_fista_step(const void* workspace, double* omega, double* sigma2) {
+  // the FISTA layout keeps the Landweber fields at the same offsets
+  return pa_landweber_step(workspace, omega, sigma2);
+}
+
+// ------------------------------------------------------ dense matrix path
+
+namespace {
+constexpr size_t kDenseMax = size_t(1) << 40;
+
+// Validates g (as the operators do) and sets *bytes to the matrix size.
+pa_status dense_bytes(const pa_geometry* g, pa_dtype dtype, pa::Plan* pl, size_t* bytes) {
+  *bytes = 0;
+  pa_status st = plan_or_fail(g, dtype, pl);
+  if (st != PA_OK) return st;
+  const double n = (double)pl->M * (double)pa::dense_ld(pl->P) * (double)pl->elem;
+  if (n > (double)kDenseMax) return set_err(PA_ERR_UNSUPPORTED, "dense matrix above 2^40 bytes");
+  *bytes = std::max<size_t>((size_t)pl->M * (size_t)pa::dense_ld(pl->P) * pl->elem, 1);
+  return PA_OK;
+}
+}  // namespace
+
+size_t pa_dense_matrix_bytes(const pa_geometry* g, pa_dtype dtype) {
+  g_err.clear();
+  pa::Plan pl;
+  size_t n = 0;
+  return dense_bytes(g, dtype, &pl, &n) == PA_OK ? n : 0;
+}
+
+size_t pa_dense_adjoint_workspace_bytes(const pa_geometry* g, pa_dtype dtype) {
+  g_err.clear();
+  pa::Plan pl;
+  size_t n = 0;
+  if (dense_bytes(g, dtype, &pl, &n) != PA_OK) return 0;
+  const pa::DenseShape s = pa::dense_shape(pl.P, pl.M);
+  return std::max<size_t>(sizeof(double) * (size_t)s.nchunks * (size_t)s.ld, 256);
+}
+
+pa_status pa_dense_build(const pa_geometry* g, pa_dtype dtype, void* matrix, size_t matrix_bytes, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  size_t need = 0;
+  pa_status st = dense_bytes(g, dtype, &pl, &need);
+  if (st != PA_OK) return st;
+  if (!matrix) return set_err(PA_ERR_INVALID_ARGUMENT, "matrix is NULL");
+  if (!aligned(matrix, 16)) return set_err(PA_ERR_INVALID_ARGUMENT, "matrix is not 16-byte aligned");
+  if (matrix_bytes < need) return set_err(PA_ERR_WORKSPACE, "matrix smaller than pa_dense_matrix_bytes()");
+  PA_HIP(pa::launch_dense_build(g, dtype, matrix, static_cast<hipStream_t>(hip_stream)), "dense build");
+  return PA_OK;
+}
+
+pa_status pa_dense_forward(const pa_geometry* g, pa_dtype dtype, const void* matrix, size_t matrix_bytes,
+                           const void* x, void* y, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  size_t need = 0;
+  pa_status st = dense_bytes(g, dtype, &pl, &need);
+  if (st != PA_OK) return st;
+  if (!matrix) return set_err(PA_ERR_INVALID_ARGUMENT, "matrix is NULL");
+  if (!aligned(matrix, 16)) return set_err(PA_ERR_INVALID_ARGUMENT, "matrix is not 16-byte aligned");
+  if (matrix_bytes < need) return set_err(PA_ERR_WORKSPACE, "matrix smaller than pa_dense_matrix_bytes()");
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if (pl.P > 0 && !aligned(x, 16)) return set_err(PA_ERR_INVALID_ARGUMENT, "x is not 16-byte aligned");
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem) || overlap(matrix, need, y, pl.M * pl.elem))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "y overlaps x or the matrix");
+  PA_HIP(pa::launch_dense_forward(g, dtype, matrix, x, y, static_cast<hipStream_t>(hip_stream)), "dense forward");
+  return PA_OK;
+}
+
+pa_status pa_dense_adjoint(const pa_geometry* g, pa_dtype dtype, const void* matrix, size_t matrix_bytes,
+                           const void* y, void* x, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  size_t need = 0;
+  pa_status st = dense_bytes(g, dtype, &pl, &need);
+  if (st != PA_OK) return st;
+  if (!matrix) return set_err(PA_ERR_INVALID_ARGUMENT, "matrix is NULL");
+  if (!aligned(matrix, 16)) return set_err(PA_ERR_INVALID_ARGUMENT, "matrix is not 16-byte aligned");
+  if (matrix_bytes < need) return set_err(PA_ERR_WORKSPACE, "matrix smaller than pa_dense_matrix_bytes()");
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  const pa::DenseShape sh = pa::dense_shape(pl.P, pl.M);
+  const size_t wneed = std::max<size_t>(sizeof(double) * (size_t)sh.nchunks * (size_t)sh.ld, 256);
+  if (!workspace) return set_err(PA_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (workspace_bytes < wneed) return set_err(PA_ERR_WORKSPACE, "workspace smaller than pa_dense_adjoint_workspace_bytes()");
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem) || overlap(matrix, need, x, pl.P * pl.elem) ||
+      overlap(workspace, wneed, x, pl.P * pl.elem) || overlap(workspace, wneed, matrix, need) ||
+      overlap(workspace, wneed, y, pl.M * pl.elem))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "x, y, the matrix and the workspace must not overlap");
+  PA_HIP(pa::launch_dense_adjoint(g, dtype, matrix, y, x, workspace, static_cast<hipStream_t>(hip_stream)),
+         "dense adjoint");
   return PA_OK;
 }
 

@@ -410,4 +410,154 @@ hipError_t launch_lw_final(const double* part_r, int gr, const double* part_x, i
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------ proximal gradient (FISTA)
+// Objective ||A x - y||^2 + lambda ||x||^2 + beta TV_eps(x) + alpha ||x||_1
+// (Eq. 8 with identity transforms).  TV_eps(z) = sum_p m_p with
+// m_p = sqrt(dx_p^2 + dy_p^2 + eps^2) over forward differences of the 2D
+// image (zero past the last column and row); its gradient at p collects
+// dx/m of the pixel to the left, dy/m of the pixel above and -(dx + dy)/m of
+// p itself.  Every per-pixel value is formed in FP64 from the stored z.
+
+// Forward differences of z at (ix, iy) and their m.
+template <typename T>
+__device__ __forceinline__ double tv_m(const T* __restrict__ z, int ix, int iy, int nx, int ny, double eps2,
+                                       double* dx, double* dy) {
+  const int64_t p = (int64_t)iy * nx + ix;
+  const double zp = (double)z[p];
+  *dx = ix + 1 < nx ? (double)z[p + 1] - zp : 0.0;
+  *dy = iy + 1 < ny ? (double)z[p + nx] - zp : 0.0;
+  return sqrt(*dx * *dx + *dy * *dy + eps2);
+}
+
+__device__ __forceinline__ double shrink(double v, double tau, int nonneg) {
+  if (nonneg) return v > tau ? v - tau : 0.0;
+  return v > tau ? v - tau : (v < -tau ? v + tau : 0.0);
+}
+
+// One proximal step at the extrapolated point z, whose A^T (y - A z) - lambda z
+// is s:  x_new = shrink(z + omega (s - beta/2 dTV(z)), omega alpha / 2),
+// z_next = x_new + mu (x_new - x_old).  x is updated in place; z_next is a
+// different buffer from z (neighbours of z are read).  Partials: TV(z) and
+// ||z||_1 (the objective at z).  beta == 0 skips the TV term (any ndim).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fista_step_kernel(const T* __restrict__ z, const T* __restrict__ s,
+                                                            T* __restrict__ x, T* __restrict__ zn, int nx, int ny,
+                                                            int64_t np, double beta, double eps, double alpha,
+                                                            const double* __restrict__ omega, double mu, int nonneg,
+                                                            double* __restrict__ part_tv, double* __restrict__ part_l1) {
+  __shared__ double red[4];
+  const double w = *omega;
+  const double tau = w * alpha * 0.5;
+  const double eps2 = eps * eps;
+  double acc_tv = 0.0, acc_l1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < np; i += (int64_t)gridDim.x * kBlock) {
+    const double zi = (double)z[i];
+    acc_l1 += fabs(zi);
+    double gtv = 0.0;
+    if (beta != 0.0) {
+      const int ix = (int)(i % nx), iy = (int)(i / nx);
+      double dx, dy, ex, ey;
+      const double m = tv_m(z, ix, iy, nx, ny, eps2, &dx, &dy);
+      acc_tv += m;
+      gtv = -(dx + dy) / m;
+      if (ix > 0) {
+        const double ml = tv_m(z, ix - 1, iy, nx, ny, eps2, &ex, &ey);
+        gtv += ex / ml;
+      }
+      if (iy > 0) {
+        const double mu_ = tv_m(z, ix, iy - 1, nx, ny, eps2, &ex, &ey);
+        gtv += ey / mu_;
+      }
+    }
+    const double v = zi + w * ((double)s[i] - 0.5 * beta * gtv);
+    const T xn = (T)shrink(v, tau, nonneg);
+    const double xd = (double)xn;
+    zn[i] = (T)(xd + mu * (xd - (double)x[i]));
+    x[i] = xn;
+  }
+  acc_tv = block_sum(acc_tv, red);
+  acc_l1 = block_sum(acc_l1, red);
+  if (threadIdx.x == 0) {
+    part_tv[blockIdx.x] = acc_tv;
+    part_l1[blockIdx.x] = acc_l1;
+  }
+}
+
+// Partials of ||v||^2, TV(v) (when beta != 0) and ||v||_1 (the objective at
+// the final iterate).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fista_terms_kernel(const T* __restrict__ v, int nx, int ny, int64_t np,
+                                                             double beta, double eps, double* __restrict__ part_n,
+                                                             double* __restrict__ part_tv,
+                                                             double* __restrict__ part_l1) {
+  __shared__ double red[4];
+  const double eps2 = eps * eps;
+  double a2 = 0.0, atv = 0.0, a1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < np; i += (int64_t)gridDim.x * kBlock) {
+    const double t = (double)v[i];
+    a2 += t * t;
+    a1 += fabs(t);
+    if (beta != 0.0) {
+      double dx, dy;
+      atv += tv_m(v, (int)(i % nx), (int)(i / nx), nx, ny, eps2, &dx, &dy);
+    }
+  }
+  a2 = block_sum(a2, red);
+  atv = block_sum(atv, red);
+  a1 = block_sum(a1, red);
+  if (threadIdx.x == 0) {
+    part_n[blockIdx.x] = a2;
+    part_tv[blockIdx.x] = atv;
+    part_l1[blockIdx.x] = a1;
+  }
+}
+
+// hist[k] = ||r||^2 + lambda ||v||^2 + beta TV(v) + alpha ||v||_1 from partials.
+__global__ void fista_hist_kernel(const double* __restrict__ part_r, int gr, const double* __restrict__ part_n, int gn,
+                                  const double* __restrict__ part_tv, const double* __restrict__ part_l1, int gp,
+                                  double lambda, double beta, double alpha, double* __restrict__ hist, int k) {
+  __shared__ double red[4];
+  const double rr = sum_partials(part_r, gr, red);
+  const double nn = sum_partials(part_n, gn, red);
+  const double tv = beta != 0.0 ? sum_partials(part_tv, gp, red) : 0.0;
+  const double l1 = sum_partials(part_l1, gp, red);
+  if (threadIdx.x == 0) hist[k] = rr + lambda * nn + beta * tv + alpha * l1;
+}
+
+hipError_t launch_fista_step(pa_dtype dt, const void* z, const void* s, void* x, void* zn, int nx, int ny, int64_t np,
+                             double beta, double eps, double alpha, const double* omega, double mu, int nonneg,
+                             double* part_tv, double* part_l1, hipStream_t st) {
+  const int g = blas_grid(np);
+  if (dt == PA_F32)
+    fista_step_kernel<float><<<g, kBlock, 0, st>>>(static_cast<const float*>(z), static_cast<const float*>(s),
+                                                   static_cast<float*>(x), static_cast<float*>(zn), nx, ny, np, beta,
+                                                   eps, alpha, omega, mu, nonneg, part_tv, part_l1);
+  else
+    fista_step_kernel<double><<<g, kBlock, 0, st>>>(static_cast<const double*>(z), static_cast<const double*>(s),
+                                                    static_cast<double*>(x), static_cast<double*>(zn), nx, ny, np,
+                                                    beta, eps, alpha, omega, mu, nonneg, part_tv, part_l1);
+  return hipGetLastError();
+}
+
+hipError_t launch_fista_terms(pa_dtype dt, const void* v, int nx, int ny, int64_t np, double beta, double eps,
+                              double* part_n, double* part_tv, double* part_l1, hipStream_t st) {
+  const int g = blas_grid(np);
+  if (dt == PA_F32)
+    fista_terms_kernel<float><<<g, kBlock, 0, st>>>(static_cast<const float*>(v), nx, ny, np, beta, eps, part_n,
+                                                    part_tv, part_l1);
+  else
+    fista_terms_kernel<double><<<g, kBlock, 0, st>>>(static_cast<const double*>(v), nx, ny, np, beta, eps, part_n,
+                                                     part_tv, part_l1);
+  return hipGetLastError();
+}
+
+hipError_t launch_fista_hist(const double* part_r, int gr, const double* part_n, int gn, const double* part_tv,
+                             const double* part_l1, int gp, double lambda, double beta, double alpha, double* hist,
+                             int k, hipStream_t st) {
+  if (!hist) return hipSuccess;
+  fista_hist_kernel<<<1, kBlock, 0, st>>>(part_r, gr, part_n, gn, part_tv, part_l1, gp, lambda, beta, alpha, hist, k);
+  return hipGetLastError();
+}
+
 }  // namespace pa

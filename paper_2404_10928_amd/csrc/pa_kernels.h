@@ -45,6 +45,17 @@ hipError_t launch_lw_step(pa_dtype dt, void* x, const void* s, int64_t np, const
 hipError_t launch_lw_final(const double* part_r, int gr, const double* part_x, int gx, double lambda, double* hist,
                            int k, hipStream_t st);
 
+// Proximal gradient (FISTA) on the l1 + TV objective: one step at the
+// extrapolated point z, the objective's terms at a vector, and a history entry.
+hipError_t launch_fista_step(pa_dtype dt, const void* z, const void* s, void* x, void* zn, int nx, int ny, int64_t np,
+                             double beta, double eps, double alpha, const double* omega, double mu, int nonneg,
+                             double* part_tv, double* part_l1, hipStream_t st);   // blas_grid(np) partials
+hipError_t launch_fista_terms(pa_dtype dt, const void* v, int nx, int ny, int64_t np, double beta, double eps,
+                              double* part_n, double* part_tv, double* part_l1, hipStream_t st);
+hipError_t launch_fista_hist(const double* part_r, int gr, const double* part_n, int gn, const double* part_tv,
+                             const double* part_l1, int gp, double lambda, double beta, double alpha, double* hist,
+                             int k, hipStream_t st);
+
 // ------------------------------------------------------------------ batches
 
 // Index of the frame whose block range of one batched launch contains global

@@ -332,6 +332,19 @@ LwLayout lw_layout(const Plan& plan) {
   return L;
 }
 
+FistaLayout fista_layout(const Plan& plan) {
+  FistaLayout F{};
+  const size_t A = 256;
+  F.lw = lw_layout(plan);
+  size_t off = F.lw.total;
+  F.part_tv = off; off = align_up(off + sizeof(double) * F.lw.g_p, A);
+  F.part_l1 = off; off = align_up(off + sizeof(double) * F.lw.g_p, A);
+  F.vec_z0 = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  F.vec_z1 = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  F.total = off;
+  return F;
+}
+
 pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, BatchPlan* bp,
                           std::string* msg, bool use_tuning) {
   if (!bp) return fail(msg, PA_ERR_INVALID_ARGUMENT, "batch plan pointer is NULL");

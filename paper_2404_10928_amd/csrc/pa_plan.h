@@ -208,4 +208,13 @@ struct LwLayout {
 };
 LwLayout lw_layout(const Plan& plan);
 
+// Proximal-gradient (FISTA) workspace layout: the Landweber fields (status,
+// step and eigenvalue at the same offsets) plus the TV and l1 partials and
+// the two extrapolated points z_k, z_{k+1} used alternately.
+struct FistaLayout {
+  LwLayout lw;
+  size_t part_tv, part_l1, vec_z0, vec_z1, total;
+};
+FistaLayout fista_layout(const Plan& plan);
+
 }  // namespace pa

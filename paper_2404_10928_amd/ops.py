@@ -470,3 +470,115 @@ def landweber(y: torch.Tensor, geom, iters: int, lam: float, omega: float = 0.0,
         sv.solve(y.contiguous(), x, x0_zero=False)
     om, s2 = sv.step()
     return x, sv.history.clone(), om, s2
+
+
+class FistaSolver:
+    """Workspace and history of repeated FISTA solves of
+    ||A x - y||^2 + lam ||x||^2 + beta TV_eps(x) + alpha ||x||_1 on one geometry.
+
+    omega > 0 fixes the step; omega == 0 estimates it on the GPU with
+    power_iters power-iteration steps (omega = 1 / (sigma2 + lam + 4 beta / eps)).
+    nonneg adds the constraint x >= 0.  history[k] = F(z_k) for k < iters and
+    F(x_iters) last."""
+
+    def __init__(self, geom, dtype: torch.dtype, iters: int, lam: float, alpha: float, beta: float,
+                 eps: float = 1e-2, omega: float = 0.0, power_iters: int = 30, nonneg: bool = False,
+                 graph: bool = True, device=None):
+        self.geom = as_device_geometry(geom, device)
+        self.dtype = dtype
+        self.iters, self.lam, self.alpha, self.beta = int(iters), float(lam), float(alpha), float(beta)
+        self.eps, self.omega, self.power_iters = float(eps), float(omega), int(power_iters)
+        self.nonneg, self.graph = bool(nonneg), graph
+        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._cg = self.geom.c_struct()
+        lib = _lib.load()
+        n = lib.pa_fista_workspace_bytes(ctypes.byref(self._cg), self._code)
+        if n == 0:
+            raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
+        self.workspace = torch.empty(int(n), dtype=torch.uint8, device=self.geom.device)
+        self.history = torch.zeros(self.iters + 1, dtype=torch.float64, device=self.geom.device)
+
+    def solve(self, y: torch.Tensor, x: torch.Tensor | None = None) -> torch.Tensor:
+        g = self.geom
+        if x is None:
+            x = torch.empty(g.image_shape, dtype=self.dtype, device=y.device)
+        _check_tensor(y, g.n_sensors * g.n_samples, "y")
+        _check_tensor(x, g.n_pixels, "x")
+        if y.dtype != self.dtype or x.dtype != self.dtype:
+            raise TypeError("y and x must match the solver dtype")
+        flags = (_lib.PA_NONNEG if self.nonneg else 0) | (_lib.PA_USE_GRAPH if self.graph else 0)
+        _lib.check(_lib.load().pa_fista_solve(ctypes.byref(self._cg), self._code, y.data_ptr() or None,
+                                              x.data_ptr() or None, self.iters, self.lam, self.alpha, self.beta,
+                                              self.eps, self.omega, self.power_iters, flags,
+                                              self.workspace.data_ptr(), self.workspace.numel(),
+                                              self.history.data_ptr(), _stream(y.device)))
+        return x
+
+    def step(self):
+        """(omega used, sigma2 estimate) of the last solve (synchronises)."""
+        torch.cuda.synchronize(self.geom.device)
+        om, s2 = ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.load().pa_fista_step(self.workspace.data_ptr(), ctypes.byref(om), ctypes.byref(s2)))
+        return om.value, s2.value
+
+
+def fista(y: torch.Tensor, geom, iters: int, lam: float, alpha: float, beta: float, eps: float = 1e-2,
+          omega: float = 0.0, power_iters: int = 30, nonneg: bool = False, graph: bool = True):
+    """FISTA on the l1 + TV objective from x0 = 0.  Returns (x, history[iters+1], omega, sigma2)."""
+    sv = FistaSolver(geom, y.dtype, iters, lam, alpha, beta, eps, omega, power_iters, nonneg, graph=graph,
+                     device=y.device)
+    x = sv.solve(y.contiguous())
+    om, s2 = sv.step()
+    return x, sv.history.clone(), om, s2
+
+
+class DenseMatrix:
+    """The dense time-domain matrix of a geometry (the paper's kn), built on
+    the GPU and applied by HBM-bound matrix-vector products.  Holds
+    S * K * round_up(P, 32) elements of device memory."""
+
+    def __init__(self, geom, dtype: torch.dtype = torch.float64, device=None):
+        self.geom = as_device_geometry(geom, device)
+        self.dtype = dtype
+        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._cg = self.geom.c_struct()
+        lib = _lib.load()
+        n = lib.pa_dense_matrix_bytes(ctypes.byref(self._cg), self._code)
+        if n == 0:
+            raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
+        w = lib.pa_dense_adjoint_workspace_bytes(ctypes.byref(self._cg), self._code)
+        self.matrix = torch.empty(int(n), dtype=torch.uint8, device=self.geom.device)
+        self.workspace = torch.empty(int(w), dtype=torch.uint8, device=self.geom.device)
+        self.ld = (self.geom.n_pixels + 31) // 32 * 32
+        _lib.check(lib.pa_dense_build(ctypes.byref(self._cg), self._code, self.matrix.data_ptr(), self.matrix.numel(),
+                                      _stream(self.geom.device)))
+
+    def view(self) -> torch.Tensor:
+        """The matrix as a [S*K][ld] tensor (a view of the same memory)."""
+        g = self.geom
+        return self.matrix.view(self.dtype).view(g.n_sensors * g.n_samples, self.ld)
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        g = self.geom
+        _check_tensor(x, g.n_pixels, "x")
+        if x.dtype != self.dtype:
+            raise TypeError("x must match the matrix dtype")
+        y = torch.empty(g.data_shape, dtype=self.dtype, device=x.device) if out is None else out
+        _check_tensor(y, g.n_sensors * g.n_samples, "y")
+        _lib.check(_lib.load().pa_dense_forward(ctypes.byref(self._cg), self._code, self.matrix.data_ptr(),
+                                                self.matrix.numel(), x.data_ptr() or None, y.data_ptr() or None,
+                                                _stream(x.device)))
+        return y
+
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        g = self.geom
+        _check_tensor(y, g.n_sensors * g.n_samples, "y")
+        if y.dtype != self.dtype:
+            raise TypeError("y must match the matrix dtype")
+        x = torch.empty(g.image_shape, dtype=self.dtype, device=y.device) if out is None else out
+        _check_tensor(x, g.n_pixels, "x")
+        _lib.check(_lib.load().pa_dense_adjoint(ctypes.byref(self._cg), self._code, self.matrix.data_ptr(),
+                                                self.matrix.numel(), y.data_ptr() or None, x.data_ptr() or None,
+                                                self.workspace.data_ptr(), self.workspace.numel(),
+                                                _stream(y.device)))
+        return x

@@ -208,3 +208,74 @@ def test_landweber_argument_checks_on_host(lib):
     assert solve(ws=None) == 3
     assert solve(wsb=n - 1) == 3
     assert solve(ws=(1 << 32) + 8) == 3
+
+
+def test_fista_argument_checks_on_host(lib):
+    vp = ctypes.c_void_p
+    d = ctypes.c_double
+    lib.pa_fista_workspace_bytes.argtypes = [ctypes.POINTER(Geom), ctypes.c_int]
+    lib.pa_fista_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_fista_solve.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, vp, vp, ctypes.c_int32, d, d, d, d, d,
+                                   ctypes.c_int32, ctypes.c_uint32, vp, ctypes.c_size_t, vp, vp]
+    g = good()
+    n = lib.pa_fista_workspace_bytes(ctypes.byref(g), 0)
+    P, M = 64 * 48, 32 * 300
+    assert n >= 4 * (4 * P + 2 * M) and n > lib.pa_landweber_workspace_bytes(ctypes.byref(g), 0)
+
+    def solve(it=5, lam=1e-3, al=1.0, be=1e-3, eps=1e-2, om=0.0, pw=30, flags=4, ws=1 << 32, wsb=n, geom=g):
+        return lib.pa_fista_solve(ctypes.byref(geom), 0, 1 << 20, 1 << 24, it, lam, al, be, eps, om, pw, flags, ws,
+                                  wsb, None, None)
+    assert solve(it=-1) == 1
+    assert solve(lam=-1.0) == 1
+    assert solve(al=-1.0) == 1
+    assert solve(al=float("nan")) == 1
+    assert solve(be=-1.0) == 1
+    assert solve(eps=0.0) == 1
+    assert solve(om=-0.5) == 1
+    assert solve(om=0.0, pw=0) == 1
+    assert solve(flags=1) == 1          # PA_X0_ZERO is not a FISTA flag: it always starts from 0
+    assert solve(flags=8) == 1
+    assert solve(ws=None) == 3
+    assert solve(wsb=n - 1) == 3
+    assert solve(ws=(1 << 32) + 8) == 3
+    # the TV term needs a 2D image; without it a volume is accepted up to the workspace check
+    g3 = good()
+    g3.ndim, g3.nz = 3, 8
+    sens3 = (ctypes.c_double * (3 * 32))()
+    g3.sensors = ctypes.cast(sens3, vp)
+    assert solve(geom=g3, be=1e-3) == 2
+    n3 = lib.pa_fista_workspace_bytes(ctypes.byref(g3), 0)
+    assert n3 > 0 and solve(geom=g3, be=0.0, ws=None, wsb=n3) == 3
+
+
+def test_dense_argument_checks_on_host(lib):
+    vp = ctypes.c_void_p
+    gp = ctypes.POINTER(Geom)
+    lib.pa_dense_matrix_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_dense_matrix_bytes.restype = ctypes.c_size_t
+    lib.pa_dense_adjoint_workspace_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_dense_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_dense_build.argtypes = [gp, ctypes.c_int, vp, ctypes.c_size_t, vp]
+    lib.pa_dense_forward.argtypes = [gp, ctypes.c_int, vp, ctypes.c_size_t, vp, vp, vp]
+    lib.pa_dense_adjoint.argtypes = [gp, ctypes.c_int, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_size_t, vp]
+    g = good()
+    M, P = 32 * 300, 64 * 48
+    assert lib.pa_dense_matrix_bytes(ctypes.byref(g), 1) == M * P * 8        # P is a multiple of 32
+    assert lib.pa_dense_matrix_bytes(ctypes.byref(g), 0) == M * P * 4
+    g.nx = 63                                                                # ld rounds 63 * 48 up to 3040
+    assert lib.pa_dense_matrix_bytes(ctypes.byref(g), 1) == M * 3040 * 8
+    w = lib.pa_dense_adjoint_workspace_bytes(ctypes.byref(g), 1)
+    assert w >= 8 * 3040 and w % (8 * 3040) == 0
+    n = lib.pa_dense_matrix_bytes(ctypes.byref(g), 1)
+    assert lib.pa_dense_build(ctypes.byref(g), 1, None, n, None) == 1
+    assert lib.pa_dense_build(ctypes.byref(g), 1, (1 << 32) + 8, n, None) == 1      # alignment
+    assert lib.pa_dense_build(ctypes.byref(g), 1, 1 << 32, n - 1, None) == 3
+    assert lib.pa_dense_forward(ctypes.byref(g), 1, 1 << 36, n, None, 1 << 20, None) == 1
+    assert lib.pa_dense_forward(ctypes.byref(g), 1, 1 << 36, n, 1 << 20, (1 << 36) + 64, None) == 1   # y inside A
+    assert lib.pa_dense_adjoint(ctypes.byref(g), 1, 1 << 36, n, 1 << 20, 1 << 24, None, w, None) == 3
+    assert lib.pa_dense_adjoint(ctypes.byref(g), 1, 1 << 36, n, 1 << 20, 1 << 24, 1 << 30, w - 8, None) == 3
+    g.dt = -1.0
+    assert lib.pa_dense_matrix_bytes(ctypes.byref(g), 1) == 0
+    g = good()
+    g.nx, g.ny, g.n_sensors, g.n_samples = 4096, 4096, 1024, 4096          # ~5e14 bytes
+    assert lib.pa_dense_matrix_bytes(ctypes.byref(g), 1) == 0
