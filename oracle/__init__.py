@@ -58,6 +58,10 @@ def _configure(lib):
         lib.or_power_sigma2.restype = ctypes.c_double
         lib.or_tv2d.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, dp]
         lib.or_tv2d.restype = ctypes.c_double
+        lib.or_freq_forward.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, dp, dp,
+                                        ctypes.c_int]
+        lib.or_freq_adjoint.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, dp, dp,
+                                        ctypes.c_int]
         lib.or_fista.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                  dp, dp, ctypes.c_int]
@@ -185,6 +189,30 @@ def fista(g, y, iters, lam, alpha, beta, eps, omega, nonneg=False, x_history=Fal
                     _dp(hx) if hx is not None else None, _threads(threads)) != 0:
         raise ValueError("oracle: bad arguments")
     return x, hz, hx
+
+
+def freq_forward(g, x, f0, df, nf, threads=None) -> np.ndarray:
+    """Y = K x for the frequency-domain matrix of Eq. 7; Y is complex [S][nf]."""
+    lib = _load()
+    cg, keep = _geom(g)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    assert x.size == g.n_pixels
+    Y = np.empty((g.n_sensors, int(nf), 2), dtype=np.float64)
+    if lib.or_freq_forward(ctypes.byref(cg), float(f0), float(df), int(nf), _dp(x), _dp(Y), _threads(threads)) != 0:
+        raise ValueError("oracle: bad arguments")
+    return Y[..., 0] + 1j * Y[..., 1]
+
+
+def freq_adjoint(g, Y, f0, df, nf, threads=None) -> np.ndarray:
+    """x = Re(K^H Y) for complex Y [S][nf]."""
+    lib = _load()
+    cg, keep = _geom(g)
+    Y = np.asarray(Y, dtype=np.complex128).reshape(g.n_sensors, int(nf))
+    Yi = np.ascontiguousarray(np.stack([Y.real, Y.imag], -1))
+    x = np.empty(g.image_shape, dtype=np.float64)
+    if lib.or_freq_adjoint(ctypes.byref(cg), float(f0), float(df), int(nf), _dp(Yi), _dp(x), _threads(threads)) != 0:
+        raise ValueError("oracle: bad arguments")
+    return x
 
 
 def tv2d(x, eps=1e-8):

@@ -358,3 +358,63 @@ int or_fista(const or_geom* g, const double* y, double* x, int iters, double lam
   free(r); free(z); free(grad); free(tvg); free(xn);
   return 0;
 }
+
+#define OR_TWO_PI 6.283185307179586476925286766559
+
+/* Frequency-domain measurement matrix (Eq. 7):
+ *   K(s, n)_p = i c k_n exp(-i k_n R_ps) / R_ps,   k_n = 2 pi f_n / c,
+ *   f_n = f0 + n df, n = 0 .. nf-1,
+ * so with c k_n = 2 pi f_n and e^{-i phi} = cos(phi) - i sin(phi):
+ *   Re K = 2 pi f_n sin(k_n R) / R,   Im K = 2 pi f_n cos(k_n R) / R.
+ * Y is complex, stored interleaved [S][nf][2] (re, im).  The time-domain
+ * fields dt, t0 and n_samples of the geometry are not used.
+ * or_freq_forward: Y = K x for a real image x.
+ * or_freq_adjoint: x = Re(K^H Y), the adjoint for the real inner product
+ *   <Y, Z> = sum Re(Y) Re(Z) + Im(Y) Im(Z). */
+int or_freq_forward(const or_geom* g, double f0, double df, int32_t nf, const double* x, double* Y,
+                    int threads) {
+  if (!geom_ok(g) || nf < 0) return -1;
+  const int32_t S = g->n_sensors;
+  const int64_t P = npix(g);
+  set_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t s = 0; s < S; ++s) {
+    for (int32_t n = 0; n < nf; ++n) {
+      const double fn = f0 + n * df;
+      const double kn = OR_TWO_PI * fn / g->c;
+      double re = 0.0, im = 0.0;
+      for (int64_t p = 0; p < P; ++p) {
+        const double R = dist(g, p, s);
+        re += x[p] * OR_TWO_PI * fn * sin(kn * R) / R;
+        im += x[p] * OR_TWO_PI * fn * cos(kn * R) / R;
+      }
+      Y[((int64_t)s * nf + n) * 2 + 0] = re;
+      Y[((int64_t)s * nf + n) * 2 + 1] = im;
+    }
+  }
+  return 0;
+}
+
+int or_freq_adjoint(const or_geom* g, double f0, double df, int32_t nf, const double* Y, double* x,
+                    int threads) {
+  if (!geom_ok(g) || nf < 0) return -1;
+  const int32_t S = g->n_sensors;
+  const int64_t P = npix(g);
+  set_threads(threads);
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < P; ++p) {
+    double acc = 0.0;
+    for (int32_t s = 0; s < S; ++s) {
+      const double R = dist(g, p, s);
+      for (int32_t n = 0; n < nf; ++n) {
+        const double fn = f0 + n * df;
+        const double kn = OR_TWO_PI * fn / g->c;
+        const double kre = OR_TWO_PI * fn * sin(kn * R) / R;
+        const double kim = OR_TWO_PI * fn * cos(kn * R) / R;
+        acc += kre * Y[((int64_t)s * nf + n) * 2 + 0] + kim * Y[((int64_t)s * nf + n) * 2 + 1];
+      }
+    }
+    x[p] = acc;
+  }
+  return 0;
+}

@@ -70,6 +70,14 @@ double or_tv2d(const double* x, int32_t nx, int32_t ny, double eps, double* grad
 int or_fista(const or_geom* g, const double* y, double* x, int iters, double lambda, double alpha,
              double beta, double eps, double omega, int nonneg, double* hz, double* hx, int threads);
 
+/* Frequency-domain matrix of Eq. 7, K(s,n)_p = i c k_n exp(-i k_n R)/R with
+ * k_n = 2 pi (f0 + n df) / c, n = 0..nf-1.  Y: complex [S][nf][2] (re, im).
+ * Forward Y = K x (real x); adjoint x = Re(K^H Y).  Returns 0 / -1. */
+int or_freq_forward(const or_geom* g, double f0, double df, int32_t nf, const double* x, double* Y,
+                    int threads);
+int or_freq_adjoint(const or_geom* g, double f0, double df, int32_t nf, const double* Y, double* x,
+                    int threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,12 @@ MUTANTS = {
     "fista_full_threshold": ("const double tau = omega * alpha / 2.0;", "const double tau = omega * alpha;"),
     "fista_full_tv_weight": ("grad[i] += 0.5 * beta * tvg[i];", "grad[i] += beta * tvg[i];"),
     "fista_lambda_dropped": ("grad[i] += lambda * z[i];", "grad[i] += 0.0 * z[i];"),
+    "freq_sin_cos_swapped": ("re += x[p] * OR_TWO_PI * fn * sin(kn * R) / R;",
+                             "re += x[p] * OR_TWO_PI * fn * cos(kn * R) / R;"),
+    "freq_phase_sign": ("re += x[p] * OR_TWO_PI * fn * sin(kn * R) / R;",
+                        "re -= x[p] * OR_TWO_PI * fn * sin(kn * R) / R;"),
+    "freq_adjoint_imag_sign": ("+ kim * Y[((int64_t)s * nf + n) * 2 + 1];", "- kim * Y[((int64_t)s * nf + n) * 2 + 1];"),
+    "freq_frequency_index": ("const double fn = f0 + n * df;", "const double fn = f0 + (n + 1) * df;"),
     "fista_nonneg_ignores_threshold": ("if (nonneg) return v > tau ? v - tau : 0.0;",
                                        "if (nonneg) return v > 0.0 ? v : 0.0;"),
 }
@@ -56,6 +62,9 @@ PINS = [
     lambda: pins.test_fista_l1_satisfies_kkt(True),
     pins.test_fista_tv_satisfies_kkt,
     pins.test_fista_meets_the_accelerated_rate_bound,
+    pins.test_freq_point_source_quarter_cycles,
+    lambda: pins.test_freq_adjoint_identity(2),
+    pins.test_freq_is_the_spectrum_of_the_time_domain_derivative,
 ]
 
 

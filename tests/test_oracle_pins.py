@@ -457,3 +457,66 @@ def test_fista_meets_the_accelerated_rate_bound():
     bound = 2 * (2 / omega) * np.sum(xs ** 2) / (k + 1) ** 2
     assert np.all(hx[1:] - Fs <= bound)
     assert np.all(hx >= Fs * (1 - 1e-12))
+
+
+# --------------------------------------------------------------------------
+# frequency-domain matrix (Eq. 7)
+
+def test_freq_point_source_quarter_cycles():
+    """One pixel at the origin and a sensor at (3 mm, 4 mm): R = 5 mm.  With
+    c = 1500 m/s, f_n = 75 kHz * (n + 1) puts (n + 1) quarter cycles on the path,
+    so exp(-i k_n R) = (-i)^(n+1) and K = i * 2 pi f_n * (-i)^(n+1) / R:
+    2 pi f / R, -i 4 pi f_0 / R... worked out by hand below."""
+    g = Geometry(2, 1, 1, 1, 1e-4, (0.0, 0.0, 0.0), np.array([[3e-3, 4e-3]]), 8, 1e-7, 0.0)
+    Y = oracle.freq_forward(g, np.ones((1, 1)), 75e3, 75e3, 4)[0]
+    u = 2 * math.pi * 75e3 / 5e-3
+    expect = [1 * u, -2j * u, -3 * u, 4j * u]     # i (-i)^m m u for m = 1..4
+    np.testing.assert_allclose(Y.real, np.real(expect), rtol=0, atol=1e-9 * u)
+    np.testing.assert_allclose(Y.imag, np.imag(expect), rtol=0, atol=1e-9 * u)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_freq_adjoint_identity(ndim):
+    g = small_geom(ndim, n=7 if ndim == 3 else 11, S=6)
+    rng = np.random.default_rng(71)
+    x = rng.normal(size=g.image_shape)
+    Y = rng.normal(size=(g.n_sensors, 9)) + 1j * rng.normal(size=(g.n_sensors, 9))
+    KX = oracle.freq_forward(g, x, 2e5, 3.1e5, 9)
+    KtY = oracle.freq_adjoint(g, Y, 2e5, 3.1e5, 9)
+    lhs = np.sum(KX.real * Y.real + KX.imag * Y.imag)
+    rhs = np.sum(x * KtY)
+    assert abs(lhs - rhs) <= 1e-13 * np.sqrt(np.sum(np.abs(KX) ** 2) * np.sum(np.abs(Y) ** 2))
+
+
+def test_freq_rotation_by_quarter_turn_shifts_sensors():
+    g = small_geom(2, n=10, S=8)
+    rng = np.random.default_rng(72)
+    x = rng.uniform(size=g.image_shape)
+    Y = oracle.freq_forward(g, x, 1e5, 2e5, 5)
+    Yr = oracle.freq_forward(g, np.rot90(x, 1), 1e5, 2e5, 5)
+    sh = g.n_sensors // 4
+    a = np.allclose(Yr, np.roll(Y, sh, axis=0), rtol=1e-12, atol=1e-12 * np.abs(Y).max())
+    b = np.allclose(Yr, np.roll(Y, -sh, axis=0), rtol=1e-12, atol=1e-12 * np.abs(Y).max())
+    assert a or b
+
+
+def test_freq_is_the_spectrum_of_the_time_domain_derivative():
+    """K(omega) = i omega exp(-i omega R / c) / R is the Fourier transform of
+    d/dt [delta(t - R/c) / R].  The time-domain operator (pinned above) spreads
+    the delta over a unit-peak hat on the sample grid (dt times a unit-area
+    pulse), whose transform is dt exp(-i omega tau dt) up to O((omega dt)^2);
+    the sample sum's own dt cancels it, so at omega dt = 0.02
+    i omega sum_k y[s,k] exp(-i omega k dt) matches K x to ~1e-4."""
+    g = small_geom(2, n=9, S=5, K=400)
+    rng = np.random.default_rng(73)
+    x = rng.uniform(size=g.image_shape)
+    y = oracle.forward(g, x)
+    omega = 0.02 / g.dt
+    f = omega / (2 * math.pi)
+    k = np.arange(g.n_samples)
+    spec = 1j * omega * (y * np.exp(-1j * omega * k * g.dt)[None, :]).sum(1)
+    Y = oracle.freq_forward(g, x, f, 0.0, 1)[:, 0]
+    err = np.abs(Y - spec).max() / np.abs(Y).max()
+    assert err <= 2e-4
+    # a sign error in the phase or a lost i turns the match into a mismatch of order one
+    assert np.abs(np.conj(Y) - spec).max() / np.abs(Y).max() > 0.1
