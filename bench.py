@@ -234,6 +234,7 @@ def main():
         out["landweber"] = landweber_leg(pa, torch, dev, geom, y, w)
         out["fista_l1_tv"] = fista_leg(pa, torch, dev, geom, y, w)
         out["dense_matrix"] = dense_leg(pa, torch, dev)
+        out["frequency_domain"] = freq_leg(pa, torch, dev)
         out["differentiable"] = autograd_leg(pa, torch, dev)
 
     print(json.dumps(out))
@@ -371,6 +372,29 @@ def dense_leg(pa, torch, dev):
     print(f"[bench] dense 128^2 FP64: A {t_f * 1e6:.0f} us ({nbytes / t_f / 1e9:.0f} GB/s), "
           f"A^T {t_a * 1e6:.0f} us; matrix-free {t_mf * 1e6:.1f} / {t_ma * 1e6:.1f} us", file=sys.stderr, flush=True)
     return out
+
+
+def freq_leg(pa, torch, dev):
+    """The frequency-domain matrix of Eq. 7 on the 128x128 workload, at the
+    DFT bins of its traces (f_n = (n + 1) / (K dt), 256 bins up to 20 MHz):
+    Y = K x and x = Re(K^H Y), FP32 with FP64 phases and sums."""
+    from synth import make_config
+    w = make_config("C1")
+    g = pa.DeviceGeometry(w.geom, dev)
+    nf = g.n_samples // 2
+    df = 1.0 / (g.n_samples * g.dt)
+    op = pa.FreqOperator(g, df, df, nf, torch.float32, dev)
+    x = torch.from_numpy(w.x.astype(np.float32)).to(dev)
+    Y = op.forward(x)
+    xo = torch.empty_like(x)
+    t_f = _sync_time(torch, lambda: op.forward(x, Y), 10)
+    t_a = _sync_time(torch, lambda: op.adjoint(Y, xo), 10)
+    terms = g.n_pixels * g.n_sensors * nf
+    print(f"[bench] frequency domain 128^2 x 128 x {nf}: K {t_f * 1e6:.0f} us, K^H {t_a * 1e6:.0f} us",
+          file=sys.stderr, flush=True)
+    return {"workload": f"128x128 image, 128 sensors, {nf} frequencies f_n = (n+1)/(K dt), FP32",
+            "terms_per_apply": terms, "us_per_apply": {"K": t_f * 1e6, "K^H": t_a * 1e6},
+            "terms_per_s": {"K": terms / t_f, "K^H": terms / t_a}}
 
 
 def autograd_leg(pa, torch, dev):

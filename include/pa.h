@@ -204,6 +204,26 @@ size_t pa_dense_adjoint_workspace_bytes(const pa_geometry* g, pa_dtype dtype);
 pa_status pa_dense_adjoint(const pa_geometry* g, pa_dtype dtype, const void* matrix, size_t matrix_bytes,
                            const void* y, void* x, void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* ------------------------------------------------ frequency-domain operator
+ * The frequency-domain measurement matrix of Eq. 7, matrix-free:
+ *   K(s, n)_p = i c k_n exp(-i k_n R_ps) / R_ps,  k_n = 2 pi f_n / c,  f_n = f0 + n df,
+ * n = 0 .. nf-1, with R_ps clamped at r_min as in pa_forward (the geometry's
+ * dt, t0 and n_samples are not used).  Y is complex, stored as interleaved
+ * (re, im) pairs [S][nf][2] of the dtype.
+ *   pa_freq_forward: Y := K x for a real image x.
+ *   pa_freq_adjoint: x := Re(K^H Y), the adjoint for the real inner product
+ *   sum Re(Y) Re(Z) + Im(Y) Im(Z).
+ * The phase f_n R / c is formed and reduced in FP64, the sine and cosine are
+ * taken in the dtype, and every sum is FP64 in a fixed order (partial sums in
+ * the caller's workspace, >= pa_freq_workspace_bytes(), 256-byte aligned).
+ * f0, df >= 0 and finite; 0 <= nf <= 65536.  Returns 0 from the size query on
+ * invalid arguments. */
+size_t pa_freq_workspace_bytes(const pa_geometry* g, pa_dtype dtype, int32_t nf);
+pa_status pa_freq_forward(const pa_geometry* g, pa_dtype dtype, double f0, double df, int32_t nf, const void* x,
+                          void* Y, void* workspace, size_t workspace_bytes, void* hip_stream);
+pa_status pa_freq_adjoint(const pa_geometry* g, pa_dtype dtype, double f0, double df, int32_t nf, const void* Y,
+                          void* x, void* workspace, size_t workspace_bytes, void* hip_stream);
+
 /* ------------------------------------------------------------------ batches
  * Many frames of uneven image size, sensor count and trace length, each with
  * its own geometry, processed by one launch per step.  Frame i's image and

@@ -36,7 +36,8 @@ EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspac
            "pa_landweber_workspace_bytes", "pa_landweber_solve", "pa_landweber_step",
            "pa_batch_autotune_workspace_bytes", "pa_batch_autotune", "pa_fista_workspace_bytes", "pa_fista_solve",
            "pa_fista_step", "pa_dense_matrix_bytes", "pa_dense_build", "pa_dense_forward",
-           "pa_dense_adjoint_workspace_bytes", "pa_dense_adjoint"]
+           "pa_dense_adjoint_workspace_bytes", "pa_dense_adjoint",
+           "pa_freq_workspace_bytes", "pa_freq_forward", "pa_freq_adjoint"]
 
 
 class PaTuning(ctypes.Structure):
@@ -139,6 +140,13 @@ def load(path: str = LIB_PATH):
     lib.pa_dense_forward.restype = ctypes.c_int
     lib.pa_dense_adjoint.argtypes = [gp, ctypes.c_int, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pa_dense_adjoint.restype = ctypes.c_int
+    lib.pa_freq_workspace_bytes.argtypes = [gp, ctypes.c_int, ctypes.c_int32]
+    lib.pa_freq_workspace_bytes.restype = ctypes.c_size_t
+    for name in ("pa_freq_forward", "pa_freq_adjoint"):
+        fn = getattr(lib, name)
+        fn.argtypes = [gp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
+                       ctypes.c_size_t, vp]
+        fn.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -1,7 +1,7 @@
 """Compiles the HIP library (libpa_mi355x.so) for gfx950 with hipcc.
 
 Sources: csrc/pa_plan.cpp (host planning), csrc/pa_ops.hip (operator
-kernels), csrc/pa_blas.hip (solver kernels), csrc/pa_dense.hip (dense-matrix path), csrc/pa_api.hip (C ABI).  Objects go to _build/ at the repository root; the
+kernels), csrc/pa_blas.hip (solver kernels), csrc/pa_dense.hip (dense-matrix path), csrc/pa_freq.hip (frequency-domain operator), csrc/pa_api.hip (C ABI).  Objects go to _build/ at the repository root; the
 shared library lands next to this file so it travels with the package.
 """
 from __future__ import annotations
@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpa_mi355x.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["pa_plan.cpp", "pa_ops.hip", "pa_batch.hip", "pa_blas.hip", "pa_dense.hip", "pa_api.hip"]
+SOURCES = ["pa_plan.cpp", "pa_ops.hip", "pa_batch.hip", "pa_blas.hip", "pa_dense.hip", "pa_freq.hip", "pa_api.hip"]
 # The operator kernels never test for NaN; running them with the IEEE mode bit
 # off lets min/max skip the NaN-quieting of LDS-loaded operands.  The solver
 # kernels keep IEEE mode because they detect non-finite step sizes.

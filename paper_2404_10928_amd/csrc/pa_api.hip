@@ -16,6 +16,7 @@
 
 #include "pa.h"
 #include "pa_dense.h"
+#include "pa_freq.h"
 #include "pa_kernels.h"
 #include "pa_plan.h"
 
@@ -1255,6 +1256,66 @@ pa_status pa_dense_adjoint(const pa_geometry* g, pa_dtype dtype, const void* mat
     return set_err(PA_ERR_INVALID_ARGUMENT, "x, y, the matrix and the workspace must not overlap");
   PA_HIP(pa::launch_dense_adjoint(g, dtype, matrix, y, x, workspace, static_cast<hipStream_t>(hip_stream)),
          "dense adjoint");
+  return PA_OK;
+}
+
+// ------------------------------------------------ frequency-domain operator
+
+namespace {
+pa_status freq_check(const pa_geometry* g, pa_dtype dtype, double f0, double df, int32_t nf, pa::Plan* pl) {
+  pa_status st = plan_or_fail(g, dtype, pl);
+  if (st != PA_OK) return st;
+  if (nf < 0 || nf > 65536) return set_err(PA_ERR_INVALID_ARGUMENT, "nf must be in [0, 65536]");
+  if (!std::isfinite(f0) || f0 < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "f0 must be finite and >= 0");
+  if (!std::isfinite(df) || df < 0) return set_err(PA_ERR_INVALID_ARGUMENT, "df must be finite and >= 0");
+  return PA_OK;
+}
+
+pa_status freq_buffers(const pa::Plan& pl, int32_t nf, const void* x, const void* Y, void* workspace,
+                       size_t workspace_bytes) {
+  pa_status st;
+  const int64_t ny = 2 * (int64_t)pl.op.S * nf;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if ((st = check_vec(Y, ny, pl.elem, "Y")) != PA_OK) return st;
+  const size_t need = pa::freq_shape(pl.P, pl.op.S, nf).workspace;
+  if (!workspace) return set_err(PA_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (workspace_bytes < need) return set_err(PA_ERR_WORKSPACE, "workspace smaller than pa_freq_workspace_bytes()");
+  if (overlap(x, pl.P * pl.elem, Y, ny * pl.elem) || overlap(workspace, need, x, pl.P * pl.elem) ||
+      overlap(workspace, need, Y, ny * pl.elem))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "x, Y and the workspace must not overlap");
+  return PA_OK;
+}
+}  // namespace
+
+size_t pa_freq_workspace_bytes(const pa_geometry* g, pa_dtype dtype, int32_t nf) {
+  g_err.clear();
+  pa::Plan pl;
+  if (freq_check(g, dtype, 0.0, 0.0, nf, &pl) != PA_OK) return 0;
+  return pa::freq_shape(pl.P, pl.op.S, nf).workspace;
+}
+
+pa_status pa_freq_forward(const pa_geometry* g, pa_dtype dtype, double f0, double df, int32_t nf, const void* x,
+                          void* Y, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = freq_check(g, dtype, f0, df, nf, &pl);
+  if (st != PA_OK) return st;
+  if ((st = freq_buffers(pl, nf, x, Y, workspace, workspace_bytes)) != PA_OK) return st;
+  PA_HIP(pa::launch_freq_forward(g, dtype, f0, df, nf, x, Y, workspace, static_cast<hipStream_t>(hip_stream)),
+         "frequency-domain forward");
+  return PA_OK;
+}
+
+pa_status pa_freq_adjoint(const pa_geometry* g, pa_dtype dtype, double f0, double df, int32_t nf, const void* Y,
+                          void* x, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = freq_check(g, dtype, f0, df, nf, &pl);
+  if (st != PA_OK) return st;
+  if ((st = freq_buffers(pl, nf, x, Y, workspace, workspace_bytes)) != PA_OK) return st;
+  PA_HIP(pa::launch_freq_adjoint(g, dtype, f0, df, nf, Y, x, workspace, static_cast<hipStream_t>(hip_stream)),
+         "frequency-domain adjoint");
   return PA_OK;
 }
 

@@ -582,3 +582,49 @@ class DenseMatrix:
                                                 self.workspace.data_ptr(), self.workspace.numel(),
                                                 _stream(y.device)))
         return x
+
+
+class FreqOperator:
+    """The frequency-domain matrix of Eq. 7 on one geometry and frequency grid
+    f_n = f0 + n df (n < nf): forward(x) -> complex Y [S][nf] (stored as real
+    pairs), adjoint(Y) -> x = Re(K^H Y)."""
+
+    def __init__(self, geom, f0: float, df: float, nf: int, dtype: torch.dtype = torch.float32, device=None):
+        self.geom = as_device_geometry(geom, device)
+        self.f0, self.df, self.nf = float(f0), float(df), int(nf)
+        self.dtype = dtype
+        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._cg = self.geom.c_struct()
+        n = _lib.load().pa_freq_workspace_bytes(ctypes.byref(self._cg), self._code, self.nf)
+        if n == 0:
+            raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
+        self.workspace = torch.empty(int(n), dtype=torch.uint8, device=self.geom.device)
+
+    @property
+    def data_shape(self):
+        return (self.geom.n_sensors, self.nf, 2)
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Y as a real tensor [S][nf][2] (torch.view_as_complex gives the complex view)."""
+        g = self.geom
+        _check_tensor(x, g.n_pixels, "x")
+        if x.dtype != self.dtype:
+            raise TypeError("x must match the operator dtype")
+        Y = torch.empty(self.data_shape, dtype=self.dtype, device=x.device) if out is None else out
+        _check_tensor(Y, 2 * g.n_sensors * self.nf, "Y")
+        _lib.check(_lib.load().pa_freq_forward(ctypes.byref(self._cg), self._code, self.f0, self.df, self.nf,
+                                               x.data_ptr() or None, Y.data_ptr() or None, self.workspace.data_ptr(),
+                                               self.workspace.numel(), _stream(x.device)))
+        return Y
+
+    def adjoint(self, Y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        g = self.geom
+        _check_tensor(Y, 2 * g.n_sensors * self.nf, "Y")
+        if Y.dtype != self.dtype:
+            raise TypeError("Y must match the operator dtype")
+        x = torch.empty(g.image_shape, dtype=self.dtype, device=Y.device) if out is None else out
+        _check_tensor(x, g.n_pixels, "x")
+        _lib.check(_lib.load().pa_freq_adjoint(ctypes.byref(self._cg), self._code, self.f0, self.df, self.nf,
+                                               Y.data_ptr() or None, x.data_ptr() or None, self.workspace.data_ptr(),
+                                               self.workspace.numel(), _stream(Y.device)))
+        return x

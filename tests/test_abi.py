@@ -279,3 +279,25 @@ def test_dense_argument_checks_on_host(lib):
     g = good()
     g.nx, g.ny, g.n_sensors, g.n_samples = 4096, 4096, 1024, 4096          # ~5e14 bytes
     assert lib.pa_dense_matrix_bytes(ctypes.byref(g), 1) == 0
+
+
+def test_freq_argument_checks_on_host(lib):
+    vp = ctypes.c_void_p
+    d = ctypes.c_double
+    gp = ctypes.POINTER(Geom)
+    lib.pa_freq_workspace_bytes.argtypes = [gp, ctypes.c_int, ctypes.c_int32]
+    lib.pa_freq_workspace_bytes.restype = ctypes.c_size_t
+    for name in ("pa_freq_forward", "pa_freq_adjoint"):
+        getattr(lib, name).argtypes = [gp, ctypes.c_int, d, d, ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, vp]
+    g = good()
+    w = lib.pa_freq_workspace_bytes(ctypes.byref(g), 0, 256)
+    assert w >= 8 * 64 * 48 and w % 256 == 0 or w >= 256
+    assert lib.pa_freq_workspace_bytes(ctypes.byref(g), 0, -1) == 0
+    assert lib.pa_freq_workspace_bytes(ctypes.byref(g), 0, 65537) == 0
+    for fn in (lib.pa_freq_forward, lib.pa_freq_adjoint):
+        assert fn(ctypes.byref(g), 0, -1.0, 1e5, 256, 1 << 20, 1 << 24, 1 << 30, w, None) == 1
+        assert fn(ctypes.byref(g), 0, 1e5, float("inf"), 256, 1 << 20, 1 << 24, 1 << 30, w, None) == 1
+        assert fn(ctypes.byref(g), 0, 1e5, 1e5, 256, None, 1 << 24, 1 << 30, w, None) == 1
+        assert fn(ctypes.byref(g), 0, 1e5, 1e5, 256, 1 << 20, 1 << 24, None, w, None) == 3
+        assert fn(ctypes.byref(g), 0, 1e5, 1e5, 256, 1 << 20, 1 << 24, 1 << 30, w - 8, None) == 3
+        assert fn(ctypes.byref(g), 0, 1e5, 1e5, 256, 1 << 20, (1 << 20) + 64, 1 << 30, w, None) == 1   # x, Y overlap
