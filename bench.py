@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle CGLS iterations timed on the host")
     ap.add_argument("--quick", action="store_true", help="skip operator and CPU legs (profiling runs)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-frames and 3D legs")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated extra legs to run: batched, volume, landweber, fista, dense, freq, "
+                         "differentiable (default all)")
     ap.add_argument("--no-tune", action="store_true", help="plan by rule instead of running the autotuner")
     ap.add_argument("--calib-copy-mib", type=int, default=64,
                     help="size of a plain device copy run once (counter calibration for profiling runs)")
@@ -229,13 +232,23 @@ def main():
                   file=sys.stderr, flush=True)
 
     if not args.quick and not args.no_extras:
-        out["batched_frames"] = batched_leg(pa, torch, dev, tune=not args.no_tune)
-        out["volume_3d"] = volume_leg(pa, torch, dev, tune=not args.no_tune)
-        out["landweber"] = landweber_leg(pa, torch, dev, geom, y, w)
-        out["fista_l1_tv"] = fista_leg(pa, torch, dev, geom, y, w)
-        out["dense_matrix"] = dense_leg(pa, torch, dev)
-        out["frequency_domain"] = freq_leg(pa, torch, dev)
-        out["differentiable"] = autograd_leg(pa, torch, dev)
+        legs = set(args.legs.split(",")) if args.legs != "all" else None
+        def want(name):
+            return legs is None or name in legs
+        if want("batched"):
+            out["batched_frames"] = batched_leg(pa, torch, dev, tune=not args.no_tune)
+        if want("volume"):
+            out["volume_3d"] = volume_leg(pa, torch, dev, tune=not args.no_tune)
+        if want("landweber"):
+            out["landweber"] = landweber_leg(pa, torch, dev, geom, y, w)
+        if want("fista"):
+            out["fista_l1_tv"] = fista_leg(pa, torch, dev, geom, y, w)
+        if want("dense"):
+            out["dense_matrix"] = dense_leg(pa, torch, dev)
+        if want("freq"):
+            out["frequency_domain"] = freq_leg(pa, torch, dev)
+        if want("differentiable"):
+            out["differentiable"] = autograd_leg(pa, torch, dev)
 
     print(json.dumps(out))
     return 0

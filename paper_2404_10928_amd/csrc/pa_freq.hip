@@ -46,10 +46,13 @@ __device__ __forceinline__ double pixel_dist(const FreqGeom& g, int64_t p, int s
   return fmax(sqrt(r2), g.rmin);
 }
 
-// sin and cos of 2 pi cyc for a phase in cycles.
+// sin and cos of 2 pi cyc for a phase in cycles.  FP32: the hardware sine and
+// cosine take their argument in revolutions, so the reduced phase feeds them
+// directly (|r| <= 1/2, well inside their domain).
 __device__ __forceinline__ void sincos_cycles(double cyc, float* s, float* c) {
-  const double r = cyc - rint(cyc);   // [-1/2, 1/2], exact
-  sincospif((float)(2.0 * r), s, c);
+  const float r = (float)(cyc - rint(cyc));   // [-1/2, 1/2]; the subtraction is exact
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
 }
 __device__ __forceinline__ void sincos_cycles(double cyc, double* s, double* c) {
   const double r = cyc - rint(cyc);
@@ -89,8 +92,8 @@ __global__ void __launch_bounds__(kT) freq_fwd_kernel(FreqGeom g, const T* __res
       T sn, cs;
       sincos_cycles(fma(dn, sb[j], sa[j]), &sn, &cs);
       const double w = (double)sw[j];
-      re += w * (double)sn;
-      im += w * (double)cs;
+      re = fma(w, (double)sn, re);
+      im = fma(w, (double)cs, im);
     }
   }
   if (n < g.nf) part[((int64_t)pc * g.S + s) * g.nf + n] = make_double2(re, im);
@@ -157,7 +160,7 @@ __global__ void __launch_bounds__(kT) freq_adj_kernel(FreqGeom g, const T* __res
         for (int j = 0; j < cnt; ++j) {
           T sn, cs;
           sincos_cycles(cyc, &sn, &cs);
-          sum += (double)yr[j] * (double)sn + (double)yi[j] * (double)cs;
+          sum = fma((double)yr[j], (double)sn, fma((double)yi[j], (double)cs, sum));
           cyc += b;
         }
       }

@@ -711,10 +711,13 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __res
 // one sample per lane.  Each wave scans the window starts of the sensor's
 // forward tiles, 64 at a time, picks by ballot the tiles whose row window
 // overlaps its own 64 samples, and every lane adds its sample of those rows,
-// in increasing tile order, in FP64 (eight loads in flight); then the
-// work-group scales, writes y and forms the FP64 partial of ||y||^2.  No
-// atomics: the result is the same on every run.  Rows and window starts are
-// sensor-major, so one sensor's rows are contiguous.
+// in increasing tile order, in FP64 (kGatherLoads loads in flight, the next 64
+// window starts prefetched); then the work-group scales, writes y and forms
+// the FP64 partial of ||y||^2.  No atomics: the result is the same on every
+// run.  Rows and window starts are sensor-major, so one sensor's rows are
+// contiguous.
+constexpr int kGatherLoads = 16;
+
 template <typename T>
 __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx, const T* __restrict__ rows,
                                             const int* __restrict__ klo_tab, T* __restrict__ y,
@@ -734,19 +737,18 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
   const int wlo = k0 + wave * 64, whi = min(k0 + kn, wlo + 64);  // this wave's samples
   double acc = 0.0;
   if (wlo < whi) {
+    // window starts of the next 64 tiles are loaded while this chunk's rows are read
+    int kl_next = lane < P.n_atiles ? kt[lane] : 0;
     for (int c0 = 0; c0 < P.n_atiles; c0 += 64) {
       const int t = c0 + lane;
-      int kl = 0;
-      bool ov = false;
-      if (t < P.n_atiles) {
-        kl = kt[t];
-        ov = kl < whi && kl + P.wpa > wlo;
-      }
+      const int kl = kl_next;
+      const bool ov = t < P.n_atiles && kl < whi && kl + P.wpa > wlo;
+      if (t + 64 < P.n_atiles) kl_next = kt[t + 64];
       uint64_t m = __ballot(ov);
       while (m != 0) {
-        double v[8];
+        double v[kGatherLoads];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kGatherLoads; ++u) {
           v[u] = 0.0;
           if (m != 0) {  // wave-uniform
             const int b = __builtin_ctzll(m);
@@ -757,7 +759,7 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
           }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
+        for (int u = 0; u < kGatherLoads; ++u) acc += v[u];
       }
     }
   }
