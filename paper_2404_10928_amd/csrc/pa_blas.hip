@@ -13,6 +13,11 @@ namespace pa {
 using dev::block_sum;
 using dev::sum_partials;
 
+// Elements per thread whose loads the CGLS update kernels issue before their
+// step-size reductions (the single-frame grids give 4 per thread on the
+// image and up to 8 on the traces).
+constexpr int kPrefetch = 4;
+
 // ---------------------------------------------------------------------------
 // BLAS-1 and CGLS scalar kernels.  Grids are fixed per vector length, so the
 // FP64 partial sums are always formed in the same order.
@@ -57,16 +62,40 @@ __device__ __forceinline__ void upd_r_body(int bid, int nblk, T* __restrict__ r,
                                            int gp, double lambda, const double* __restrict__ gamma_k,
                                            double* __restrict__ alpha_k, int* __restrict__ status, int k,
                                            double* __restrict__ part_r) {
-  __shared__ double red[4];
-  const double qq = sum_partials(part_q, gq, red);
-  const double pp = sum_partials(part_p, gp, red);
+  __shared__ double red[8];
+  // The first kPrefetch elements' loads go out before the step size is
+  // known, so their latency overlaps the partial sums.
+  const int64_t stride = (int64_t)nblk * kBlock;
+  const int64_t i0 = (int64_t)bid * kBlock + threadIdx.x;
+  T rv[kPrefetch], qv[kPrefetch];
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u) {
+    const int64_t i = i0 + u * stride;
+    rv[u] = i < m ? r[i] : (T)0;
+    qv[u] = i < m ? q[i] : (T)0;
+  }
+  double sums[2];
+  dev::sum_partials_n<2>({part_q, part_p}, {gq, gp}, sums, red);
+  const double qq = sums[0], pp = sums[1];
   const double delta = qq + lambda * pp;
   const double g = *gamma_k;
   const int st = *status;
   const bool stop = st >= 0 || !(g > 0.0) || !(delta > 0.0) || !isfinite(g) || !isfinite(delta);
   const double a = stop ? 0.0 : g / delta;
   double acc = 0.0;
-  for (int64_t i = (int64_t)bid * kBlock + threadIdx.x; i < m; i += (int64_t)nblk * kBlock) {
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u) {
+    const int64_t i = i0 + u * stride;
+    if (i < m) {
+      T t = rv[u];
+      if (a != 0.0) {
+        t = (T)((double)t - a * (double)qv[u]);
+        r[i] = t;
+      }
+      acc += (double)t * (double)t;
+    }
+  }
+  for (int64_t i = i0 + kPrefetch * stride; i < m; i += stride) {
     T t = r[i];
     if (a != 0.0) {
       t = (T)((double)t - a * (double)q[i]);
@@ -93,10 +122,20 @@ __device__ __forceinline__ void dir_body(int bid, int nblk, T* __restrict__ p, c
                                          int gr, double lambda, double* __restrict__ gamma, int k,
                                          const int* __restrict__ status, double* __restrict__ hist,
                                          double* __restrict__ part_p) {
-  __shared__ double red[4];
-  const double ss = sum_partials(part_s, gs, red);
-  const double xx = sum_partials(part_x, gx, red);
-  const double rr = sum_partials(part_r, gr, red);
+  __shared__ double red[12];
+  // The first kPrefetch elements' loads go out before beta is known.
+  const int64_t stride = (int64_t)nblk * kBlock;
+  const int64_t i0 = (int64_t)bid * kBlock + threadIdx.x;
+  T sv[kPrefetch], pv[kPrefetch];
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u) {
+    const int64_t i = i0 + u * stride;
+    sv[u] = i < np ? s[i] : (T)0;
+    pv[u] = i < np ? p[i] : (T)0;
+  }
+  double sums[3];
+  dev::sum_partials_n<3>({part_s, part_x, part_r}, {gs, gx, gr}, sums, red);
+  const double ss = sums[0], xx = sums[1], rr = sums[2];
   double beta = 0.0;
   if (k >= 0) {
     const double gold = gamma[k];
@@ -104,7 +143,17 @@ __device__ __forceinline__ void dir_body(int bid, int nblk, T* __restrict__ p, c
   }
   double acc = 0.0;
   const int64_t n = np > m ? np : m;
-  for (int64_t i = (int64_t)bid * kBlock + threadIdx.x; i < n; i += (int64_t)nblk * kBlock) {
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u) {
+    const int64_t i = i0 + u * stride;
+    if (i < np) {
+      const T t = (T)((double)sv[u] + (beta != 0.0 ? beta * (double)pv[u] : 0.0));
+      p[i] = t;
+      acc += (double)t * (double)t;
+    }
+    if (i < m) q[i] = (T)0;
+  }
+  for (int64_t i = i0 + kPrefetch * stride; i < n; i += stride) {
     if (i < np) {
       const T t = (T)((double)s[i] + (beta != 0.0 ? beta * (double)p[i] : 0.0));
       p[i] = t;
