@@ -128,6 +128,36 @@ def test_c2_f32_solve(pa):
     assert off_curve(h[:, 2], h_ref[:, 2]) == [] and off_curve(h[:, 0], h_ref[:, 0]) == []
 
 
+
+def test_c2_under_autotuned_plans(pa):
+    """The 512x512 workload in the launch configuration the benchmark times:
+    the autotuner picks the tilings (recorded for every later plan of this
+    shape), then A, A^T and the 50-iteration FP32 solve meet the same gates
+    as under the planner's rules."""
+    w = make_config("C2")
+    g, y = problem(w)
+    y32, y64 = rounded(y, np.float32)
+    xg, x64 = rounded(w.x, np.float32)
+    pa.tuning_clear()
+    try:
+        t = pa.autotune(g, torch.float32)
+        print("C2 tuning:", t)
+        yf = pa.forward(torch.from_numpy(xg).to("cuda"), g).double().cpu().numpy()
+        xa = pa.adjoint(torch.from_numpy(y32).to("cuda"), g).double().cpu().numpy()
+        e_f = rel_l2(yf, oracle.forward(g, x64))
+        e_a = rel_l2(xa, oracle.adjoint(g, y64))
+        x, h, stop = gpu_cgls(pa, g, y32, w.iters, w.lam, np.float32)
+    finally:
+        pa.tuning_clear()
+    x_ref, h_ref, _ = oracle.cgls(g, y64, w.iters, w.lam)
+    err = rel_hist(h, h_ref)
+    e_x = rel_l2(x, x_ref)
+    print(f"C2 tuned: A {e_f:.2e} A^T {e_a:.2e}; iterate {e_x:.2e}; final F {err[-1, 2]:.2e} ||r|| {err[-1, 0]:.2e}")
+    assert e_f <= 1e-5 and e_a <= 1e-5
+    assert stop == -1
+    assert e_x <= 1e-4 and err[-1, 2] <= 1e-4 and err[-1, 0] <= 1e-4
+    assert off_curve(h[:, 2], h_ref[:, 2]) == [] and off_curve(h[:, 0], h_ref[:, 0]) == []
+
 def test_graph_matches_eager(pa):
     g = ring_geom(n=(64, 48), S=96, K=320)
     rng = np.random.default_rng(21)
