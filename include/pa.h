@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PA_ABI_VERSION 1
+#define PA_ABI_VERSION 2
 
 typedef enum {
   PA_OK = 0,
@@ -58,8 +58,11 @@ typedef enum {
 } pa_status;
 
 typedef enum {
-  PA_F32 = 0, /* x, y and the CGLS vectors are float; every inner product, norm, step size and the history are double on the GPU */
-  PA_F64 = 1  /* everything is double */
+  PA_F32 = 0,  /* x, y and the CGLS vectors are float; every inner product, norm, step size and the history are double on the GPU */
+  PA_F64 = 1,  /* everything is double */
+  PA_MIXED = 2 /* x, y, every vector and every sum are double; the per-pair delay and weight are formed in FP32
+                  arithmetic as in PA_F32 (FP64 for sensors near the pixels), so the operator costs about what
+                  PA_F32 does while nothing is rounded to float */
 } pa_dtype;
 
 typedef struct {
@@ -307,8 +310,11 @@ pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int
  * overwritten).  Synchronises the stream.  May allocate the forward
  * operator's internal scratch (as pa_forward does). */
 typedef struct {
-  int32_t fwd_tile[3];     /* base tiles per forward tile, per axis (0: no forward work) */
+  int32_t fwd_seg;         /* samples of one trace per forward work-group (0: no forward work) */
   int32_t adj_lds_bytes;   /* adjoint LDS budget that sets its sensor chunk (0: no adjoint work) */
+  int32_t fwd_mode;        /* forward accumulation with FP32 delay arithmetic: 1 = fixed-point tile rows,
+                              2 = FP64 bins (0 under PA_F64, which always uses FP64 bins) */
+  int32_t pad;
   double fwd_us, adj_us;   /* measured time per apply of the chosen tilings */
 } pa_tuning;
 

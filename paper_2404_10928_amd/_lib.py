@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "PA_OK", 1: "PA_ERR_INVALID_ARGUMENT", 2: "PA_ERR_UNSUPPORTED
 
 PA_F32 = 0
 PA_F64 = 1
+PA_MIXED = 2
 PA_X0_ZERO = 1
 PA_USE_GRAPH = 2
 PA_NONNEG = 4
@@ -41,8 +42,8 @@ EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspac
 
 
 class PaTuning(ctypes.Structure):
-    _fields_ = [("fwd_tile", ctypes.c_int32 * 3), ("adj_lds_bytes", ctypes.c_int32), ("fwd_us", ctypes.c_double),
-                ("adj_us", ctypes.c_double)]
+    _fields_ = [("fwd_seg", ctypes.c_int32), ("adj_lds_bytes", ctypes.c_int32), ("fwd_mode", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("fwd_us", ctypes.c_double), ("adj_us", ctypes.c_double)]
 
 
 class PaGeometry(ctypes.Structure):

@@ -92,7 +92,6 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
   void* q = ws + L.vec_q;
   void* s = ws + L.vec_s;
   void* p = ws + L.vec_p;
-  void* fwd = ws + L.fwd;
   hipError_t e;
   const int gbp = std::max(pl.bp_grid, 1);
 
@@ -101,7 +100,7 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
     if ((e = pa::launch_fill(dt, S.x, pl.P, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, nullptr, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
   } else {
-    if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
   }
   pa::CgArgs cg{S.x, p, alpha, S.lambda, part_s, part_x};
@@ -120,8 +119,8 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
                           status, S.hist, part_p, st)) != hipSuccess)
     return e;
   for (int k = 0; k < S.iters; ++k) {
-    // q = A p with the FP64 partials of ||q||^2 (the forward gather overwrites q)
-    if ((e = pa::launch_forward(pl, p, q, fwd, part_q, st)) != hipSuccess) return e;
+    // q = A p with the FP64 partials of ||q||^2
+    if ((e = pa::launch_forward(pl, p, q, part_q, st)) != hipSuccess) return e;
     if ((e = pa::launch_upd_r(dt, r, q, pl.M, part_q, L.g_q, part_p, L.g_p, S.lambda, gamma + k, alpha + k + 1, status,
                               k, part_r, st)) != hipSuccess)
       return e;
@@ -166,14 +165,13 @@ hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
   void* q = ws + L.vec_q;
   void* s = ws + L.vec_s;
   void* v = ws + L.vec_v;
-  void* fwd = ws + L.fwd;
   hipError_t e;
   // step size
   if ((e = pa::launch_fill(PA_F64, sigma2, 1, st)) != hipSuccess) return e;
   if (!(S.omega > 0.0) && pl.P > 0) {
     if ((e = pa::launch_fill_value(dt, v, pl.P, 1.0 / std::sqrt((double)pl.P), st)) != hipSuccess) return e;
     for (int it = 0; it < S.power_iters; ++it) {
-      if ((e = pa::launch_forward(pl, v, q, fwd, nullptr, st)) != hipSuccess) return e;
+      if ((e = pa::launch_forward(pl, v, q, nullptr, st)) != hipSuccess) return e;
       if (pl.bp_grid > 0 && (e = pa::launch_adjoint(pl, q, s, nullptr, st)) != hipSuccess) return e;
       if ((e = pa::launch_norm2(dt, s, pl.P, part_n, st)) != hipSuccess) return e;
       if ((e = pa::launch_pw_scale(dt, v, s, pl.P, part_n, sigma2, st)) != hipSuccess) return e;
@@ -186,7 +184,7 @@ hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
   // s = A^T r - lambda x with x unchanged (the epilogue's step is the zero that init_r writes)
   pa::CgArgs cg{S.x, S.x, alpha0, S.lambda, part_s, part_x};
   for (int k = 0; k < S.iters; ++k) {
-    if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
     if (pl.bp_grid == 0) {
       if ((e = pa::launch_fill(PA_F64, part_s, gbp, st)) != hipSuccess) return e;
@@ -199,7 +197,7 @@ hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
       return e;
   }
   // F at the final iterate
-  if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
+  if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
   if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
   if ((e = pa::launch_norm2(dt, S.x, pl.P, part_n, st)) != hipSuccess) return e;
   return pa::launch_lw_final(part_r, L.g_m, part_n, L.g_p, S.lambda, S.hist, S.iters, st);
@@ -242,7 +240,6 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
   void* s = ws + L.vec_s;
   void* v = ws + L.vec_v;
   void* zb[2] = {ws + S.F.vec_z0, ws + S.F.vec_z1};
-  void* fwd = ws + L.fwd;
   const int nonneg = (S.flags & PA_NONNEG) ? 1 : 0;
   hipError_t e;
   // step: 1 / (sigma2 + lambda + 4 beta / eps), the inverse Lipschitz constant
@@ -251,7 +248,7 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
   if (!(S.omega > 0.0) && pl.P > 0) {
     if ((e = pa::launch_fill_value(dt, v, pl.P, 1.0 / std::sqrt((double)pl.P), st)) != hipSuccess) return e;
     for (int it = 0; it < S.power_iters; ++it) {
-      if ((e = pa::launch_forward(pl, v, q, fwd, nullptr, st)) != hipSuccess) return e;
+      if ((e = pa::launch_forward(pl, v, q, nullptr, st)) != hipSuccess) return e;
       if (pl.bp_grid > 0 && (e = pa::launch_adjoint(pl, q, s, nullptr, st)) != hipSuccess) return e;
       if ((e = pa::launch_norm2(dt, s, pl.P, part_n, st)) != hipSuccess) return e;
       if ((e = pa::launch_pw_scale(dt, v, s, pl.P, part_n, sigma2, st)) != hipSuccess) return e;
@@ -268,7 +265,7 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
     void* zn = zb[(k + 1) & 1];
     // r = y - A z ; s = A^T r - lambda z with the partials of ||z||^2 (the
     // epilogue's step is the zero that init_r writes, so z is unchanged)
-    if ((e = pa::launch_forward(pl, z, q, fwd, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, z, q, nullptr, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
     if (pl.bp_grid == 0) {
       if ((e = pa::launch_fill(PA_F64, part_s, gbp, st)) != hipSuccess) return e;
@@ -288,7 +285,7 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
     t = t1;
   }
   // the objective at the final iterate
-  if ((e = pa::launch_forward(pl, S.x, q, fwd, nullptr, st)) != hipSuccess) return e;
+  if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
   if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
   if ((e = pa::launch_fista_terms(dt, S.x, S.nx, S.ny, pl.P, S.beta, S.eps, part_n, part_tv, part_l1, st)) !=
       hipSuccess)
@@ -300,7 +297,8 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
 // ------------------------------------------------------------ graph cache
 
 struct GraphKey {
-  uint64_t batch;   // 0 for single-frame solves, else the batch's id
+  uint64_t batch;   // 0 for single-frame solves, else the batch's id (renewed whenever its plan changes)
+  uint64_t epoch;   // single-frame solves: the tuning table's epoch the plan was made under
   pa_geometry g;
   pa_dtype dt;
   const void* y;
@@ -365,49 +363,6 @@ hipError_t get_graph(const GraphKey& key, Enqueue&& enqueue, hipGraphExec_t* out
   return hipSuccess;
 }
 
-// ------------------------------------------------- forward-operator scratch
-//
-// pa_forward keeps one scratch buffer per (device, stream) for the partial
-// histogram rows of the forward operator, grown on demand and kept until the
-// process ends.  Calls on one stream are ordered, so they can share it.
-
-struct ScratchEntry {
-  int device;
-  hipStream_t stream;
-  void* ptr;
-  size_t bytes;
-};
-std::mutex g_scr_mu;
-std::list<ScratchEntry>* g_scr = nullptr;
-
-hipError_t get_scratch(size_t bytes, hipStream_t st, void** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(g_scr_mu);
-  if (!g_scr) g_scr = new std::list<ScratchEntry>();
-  for (auto& en : *g_scr) {
-    if (en.device == dev && en.stream == st) {
-      if (en.bytes < bytes) {
-        // the old buffer may still be read by work already queued on this stream
-        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-        if ((e = hipFree(en.ptr)) != hipSuccess) return e;
-        en.ptr = nullptr;
-        en.bytes = 0;
-        if ((e = hipMalloc(&en.ptr, bytes)) != hipSuccess) return e;
-        en.bytes = bytes;
-      }
-      *out = en.ptr;
-      return hipSuccess;
-    }
-  }
-  void* p = nullptr;
-  if ((e = hipMalloc(&p, bytes)) != hipSuccess) return e;
-  g_scr->push_back(ScratchEntry{dev, st, p, bytes});
-  *out = p;
-  return hipSuccess;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------ batches
@@ -431,15 +386,13 @@ pa::BatchLaunch batch_launch(const pa::BatchPlan& B, unsigned char* ws, const pa
   bl.dtype = B.dtype;
   bl.ndim = B.ndim;
   bl.frac = B.frac;
-  bl.scratch = ws + L.fwd;
+  bl.ffix = B.ffix;
   bl.bp_grid = B.bp_grid;
   bl.fp_grid = B.fp_grid;
-  bl.gather_grid = B.gather_grid;
   bl.m_grid = B.m_grid;
   bl.p_grid = B.p_grid;
   bl.bp_lds = B.bp_lds;
   bl.fp_lds = B.fp_lds;
-  bl.gather_lds = B.gather_lds;
   bl.P_total = B.P_total;
   bl.M_total = B.M_total;
   return bl;
@@ -513,10 +466,10 @@ hipError_t enqueue_batch_cgls(const BatchSolve& S, hipStream_t st) {
   const int as = L.astride;
   const int hs = 3 * (S.iters + 1);
   hipError_t e;
-  // slots of frames without adjoint or gather work stay zero for the whole solve
+  // slots of frames without adjoint or forward work stay zero for the whole solve
   if ((e = pa::launch_fill(PA_F64, part_s, B.bp_slots, st)) != hipSuccess) return e;
   if ((e = pa::launch_fill(PA_F64, part_x, B.bp_slots, st)) != hipSuccess) return e;
-  if ((e = pa::launch_fill(PA_F64, part_q, B.ga_slots, st)) != hipSuccess) return e;
+  if ((e = pa::launch_fill(PA_F64, part_q, B.fp_slots, st)) != hipSuccess) return e;
   if (S.flags & PA_X0_ZERO) {
     if ((e = pa::launch_fill(B.dtype, S.x, B.P_total, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r_batched(bl, r, S.y, nullptr, part_r, status, alpha, as, st)) != hipSuccess) return e;
@@ -565,10 +518,7 @@ pa_status pa_forward(const pa_geometry* g, pa_dtype dtype, const void* x, void* 
   if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
   if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
   if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  void* scratch = nullptr;
-  if (pl.fp_grid > 0) PA_HIP(get_scratch(pl.fwd_scratch, s, &scratch), "forward scratch allocation");
-  PA_HIP(pa::launch_forward(pl, x, y, scratch, nullptr, s), "forward kernels");
+  PA_HIP(pa::launch_forward(pl, x, y, nullptr, static_cast<hipStream_t>(hip_stream)), "forward kernel");
   return PA_OK;
 }
 
@@ -599,6 +549,7 @@ size_t pa_cgls_workspace_bytes(const pa_geometry* g, pa_dtype dtype, int32_t ite
 pa_status pa_cgls_solve(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, int32_t iters, double lambda,
                         uint32_t flags, void* workspace, size_t workspace_bytes, double* history, void* hip_stream) {
   g_err.clear();
+  const uint64_t epoch = pa::tune_epoch();  // read before planning: a later tuning makes a new key
   pa::Plan pl;
   pa_status st = plan_or_fail(g, dtype, &pl);
   if (st != PA_OK) return st;
@@ -636,6 +587,7 @@ pa_status pa_cgls_solve(const pa_geometry* g, pa_dtype dtype, const void* y, voi
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   key.g = *g;
+  key.epoch = epoch;
   key.dt = dtype;
   key.y = y;
   key.x = x;
@@ -759,6 +711,7 @@ pa_status pa_batch_autotune(pa_batch* b, void* x, void* y, void* workspace, size
   {
     std::lock_guard<std::mutex> lk(b->mu);
     b->plan = std::move(cand[pick]);
+    b->id = g_batch_ids.fetch_add(1);  // graphs captured under the old plan no longer match
     if (b->pinned) {
       (void)hipHostFree(b->pinned);
       b->pinned = nullptr;
@@ -942,27 +895,33 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
     *us = best;
     return hipSuccess;
   };
-  pa::Tuning best{{0, 0, 0}, 0};
+  pa::Tuning best{0, 0, 0};
   float best_f = 3.0e38f, best_a = 3.0e38f;
   hipError_t err = hipSuccess;
-  // forward tilings
-  if (base.fp_grid > 0) {
-    int cand[8][3];
-    const int nc = pa::fwd_tile_candidates(base.ndim, cand, 8);
-    for (int i = 0; i < nc && err == hipSuccess; ++i) {
-      pa::Tuning t{{cand[i][0], cand[i][1], cand[i][2]}, 0};
-      pa::Plan pl;
-      std::string msg;
-      if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK) continue;
-      if (pl.op.msub[0] != t.fwd_tile[0] || pl.op.msub[1] != t.fwd_tile[1] || pl.op.msub[2] != t.fwd_tile[2])
-        continue;  // did not fit; the planner fell back to its own choice
-      void* scratch = nullptr;
-      if ((err = get_scratch(pl.fwd_scratch, s, &scratch)) != hipSuccess) break;
-      float us = 0.f;
-      err = time_it([&] { return pa::launch_forward(pl, x, y, scratch, nullptr, s); }, &us);
-      if (err == hipSuccess && us < best_f) {
-        best_f = us;
-        for (int a = 0; a < 3; ++a) best.fwd_tile[a] = t.fwd_tile[a];
+  // the forward kernel skips all-zero tiles, so time it on a full image
+  err = pa::launch_fill_value(dtype, x, base.P, 1.0, s);
+  if (err == hipSuccess) err = pa::launch_fill_value(dtype, y, base.M, 1.0, s);
+  // forward segment lengths (and, with FP32 delay arithmetic, both accumulation modes)
+  if (base.fp_grid > 0 && err == hipSuccess) {
+    int32_t cand[8];
+    const int nc = pa::fwd_seg_candidates(cand, 8);
+    const int nmode = dtype == PA_F64 ? 1 : 2;
+    for (int mode = 1; mode <= nmode && err == hipSuccess; ++mode) {
+      int last_seg = -1;
+      for (int i = 0; i < nc && err == hipSuccess; ++i) {
+        pa::Tuning t{cand[i], 0, dtype == PA_F64 ? 0 : mode};
+        pa::Plan pl;
+        std::string msg;
+        if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK) continue;
+        if (pl.op.fseg == last_seg) continue;  // clipped to the same segment as the previous candidate
+        last_seg = pl.op.fseg;
+        float us = 0.f;
+        err = time_it([&] { return pa::launch_forward(pl, x, y, nullptr, s); }, &us);
+        if (err == hipSuccess && us < best_f) {
+          best_f = us;
+          best.fwd_seg = pl.op.fseg;
+          best.fwd_mode = t.fwd_mode;
+        }
       }
     }
   }
@@ -972,7 +931,7 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
     const int nc = pa::adj_lds_candidates(cand, 8);
     int last_sc = -1;
     for (int i = 0; i < nc && err == hipSuccess; ++i) {
-      pa::Tuning t{{0, 0, 0}, (int32_t)cand[i]};
+      pa::Tuning t{0, (int32_t)cand[i], 0};
       pa::Plan pl;
       std::string msg;
       if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK) continue;
@@ -991,7 +950,8 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
   if (err != hipSuccess) return hip_err(err, "autotune");
   pa::tune_store(g, dtype, best);
   if (out) {
-    for (int a = 0; a < 3; ++a) out->fwd_tile[a] = best.fwd_tile[a];
+    out->fwd_seg = best.fwd_seg;
+    out->fwd_mode = best.fwd_mode;
     out->adj_lds_bytes = best.adj_lds;
     out->fwd_us = best_f < 3.0e38f ? best_f : 0.0;
     out->adj_us = best_a < 3.0e38f ? best_a : 0.0;
@@ -1016,6 +976,7 @@ pa_status pa_landweber_solve(const pa_geometry* g, pa_dtype dtype, const void* y
                              double lambda, double omega, int32_t power_iters, uint32_t flags, void* workspace,
                              size_t workspace_bytes, double* history, void* hip_stream) {
   g_err.clear();
+  const uint64_t epoch = pa::tune_epoch();  // read before planning: a later tuning makes a new key
   pa::Plan pl;
   pa_status st = plan_or_fail(g, dtype, &pl);
   if (st != PA_OK) return st;
@@ -1056,6 +1017,7 @@ pa_status pa_landweber_solve(const pa_geometry* g, pa_dtype dtype, const void* y
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   key.g = *g;
+  key.epoch = epoch;
   key.dt = dtype;
   key.y = y;
   key.x = x;
@@ -1096,6 +1058,7 @@ pa_status pa_fista_solve(const pa_geometry* g, pa_dtype dtype, const void* y, vo
                          double alpha, double beta, double eps, double omega, int32_t power_iters, uint32_t flags,
                          void* workspace, size_t workspace_bytes, double* history, void* hip_stream) {
   g_err.clear();
+  const uint64_t epoch = pa::tune_epoch();  // read before planning: a later tuning makes a new key
   pa::Plan pl;
   pa_status st = plan_or_fail(g, dtype, &pl);
   if (st != PA_OK) return st;
@@ -1142,6 +1105,7 @@ pa_status pa_fista_solve(const pa_geometry* g, pa_dtype dtype, const void* y, vo
   GraphKey key;
   std::memset(&key, 0, sizeof(key));
   key.g = *g;
+  key.epoch = epoch;
   key.dt = dtype;
   key.y = y;
   key.x = x;
@@ -1176,6 +1140,7 @@ constexpr size_t kDenseMax = size_t(1) << 40;
 // Validates g (as the operators do) and sets *bytes to the matrix size.
 pa_status dense_bytes(const pa_geometry* g, pa_dtype dtype, pa::Plan* pl, size_t* bytes) {
   *bytes = 0;
+  if (dtype == PA_MIXED) return set_err(PA_ERR_UNSUPPORTED, "the dense matrix path takes PA_F32 or PA_F64");
   pa_status st = plan_or_fail(g, dtype, pl);
   if (st != PA_OK) return st;
   const double n = (double)pl->M * (double)pa::dense_ld(pl->P) * (double)pl->elem;
@@ -1263,6 +1228,7 @@ pa_status pa_dense_adjoint(const pa_geometry* g, pa_dtype dtype, const void* mat
 
 namespace {
 pa_status freq_check(const pa_geometry* g, pa_dtype dtype, double f0, double df, int32_t nf, pa::Plan* pl) {
+  if (dtype == PA_MIXED) return set_err(PA_ERR_UNSUPPORTED, "the frequency-domain operator takes PA_F32 or PA_F64");
   pa_status st = plan_or_fail(g, dtype, pl);
   if (st != PA_OK) return st;
   if (nf < 0 || nf > 65536) return set_err(PA_ERR_INVALID_ARGUMENT, "nf must be in [0, 65536]");

@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) upd_r_batched(const FrameDesc* __restr
   const FrameDesc& F = B[find_frame<&FrameDesc::b_m>(B, nf, g)];
   const int64_t m = (int64_t)F.op.S * F.op.K;
   const size_t a0 = (size_t)F.frame * astride;
-  upd_r_body<T>(g - F.b_m, F.n_m, r + F.yo, q + F.yo, m, part_q + F.s_ga, F.n_ga > 0 ? F.n_ga : 1, part_p + F.b_p,
+  upd_r_body<T>(g - F.b_m, F.n_m, r + F.yo, q + F.yo, m, part_q + F.s_fp, F.n_fp > 0 ? F.n_fp : 1, part_p + F.b_p,
                 F.n_p, lambda, gamma + a0 + k, alpha + a0 + k + 1, status + F.frame, k, part_r + F.b_m);
 }
 

@@ -21,9 +21,9 @@ struct CgArgs {
 hipError_t launch_fill(pa_dtype dt, void* p, int64_t n, hipStream_t st);
 // x := A^T y (or the CGLS epilogue when cg != nullptr)
 hipError_t launch_adjoint(const Plan& pl, const void* y, void* x, const CgArgs* cg, hipStream_t st);
-// y := A x in two passes through `scratch` (plan.fwd_scratch bytes); when
-// part_q is not NULL it receives plan.gather_grid FP64 partial sums of ||y||^2
-hipError_t launch_forward(const Plan& pl, const void* x, void* y, void* scratch, double* part_q, hipStream_t st);
+// y := A x; when part_q is not NULL it receives max(plan.fp_grid, 1) FP64
+// partial sums of ||y||^2
+hipError_t launch_forward(const Plan& pl, const void* x, void* y, double* part_q, hipStream_t st);
 hipError_t launch_init_r(pa_dtype dt, void* r, const void* y, const void* q, int64_t m, double* part_r, int* status,
                          double* alpha0, hipStream_t st);
 hipError_t launch_upd_r(pa_dtype dt, void* r, const void* q, int64_t m, const double* part_q, int gq, const double* part_p,
@@ -79,9 +79,9 @@ struct BatchLaunch {
   pa_dtype dtype;
   int ndim;
   bool frac;                // some frame has a fractional t0 / dt
-  unsigned char* scratch;   // device forward scratch area
-  int bp_grid, fp_grid, gather_grid, m_grid, p_grid;
-  size_t bp_lds, fp_lds, gather_lds;
+  bool ffix;                // forward with fixed-point tile rows (FP32 delay arithmetic)
+  int bp_grid, fp_grid, m_grid, p_grid;
+  size_t bp_lds, fp_lds;
   int64_t P_total, M_total;
 };
 

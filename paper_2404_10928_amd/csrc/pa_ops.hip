@@ -18,29 +18,24 @@
 namespace pa {
 
 // ---------------------------------------------------------------------------
-// Single-frame kernels.  Work-group IDs are remapped so each XCD gets a
-// contiguous run of tiles (neighbouring tiles read overlapping windows).
+// Single-frame kernels.  T is the element type of the vectors, PH the type of
+// the per-pair delay arithmetic (PA_F32: float/float, PA_F64: double/double,
+// PA_MIXED: double/float).  Adjoint work-group IDs are remapped so each XCD
+// gets a contiguous run of tiles (neighbouring tiles read overlapping windows).
 
-template <typename T, int ND, bool FRAC, bool CG>
+template <typename T, typename PH, int ND, bool FRAC, bool CG>
 __global__ void __launch_bounds__(kBlock) bp_kernel(OpParams P, const T* __restrict__ y, T* __restrict__ out,
                                                      T* __restrict__ xcg, const T* __restrict__ pcg,
                                                      const double* __restrict__ alpha, double lambda,
                                                      double* __restrict__ part_s, double* __restrict__ part_x) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  bp_body<T, ND, FRAC, CG>(P, tile, tile, y, out, xcg, pcg, alpha, lambda, part_s, part_x);
+  bp_body<T, PH, ND, FRAC, CG>(P, tile, tile, y, out, xcg, pcg, alpha, lambda, part_s, part_x);
 }
 
-template <typename T, int ND, bool FRAC>
-__global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restrict__ x, T* __restrict__ rows,
-                                                     int* __restrict__ klo_tab) {
-  fp_body<T, ND, FRAC>(P, xcd_remap(blockIdx.x, gridDim.x), x, rows, klo_tab);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) fp_gather_kernel(OpParams P, const T* __restrict__ rows,
-                                                            const int* __restrict__ klo_tab, T* __restrict__ y,
-                                                            double* __restrict__ part_q) {
-  gather_body<T>(P, blockIdx.x, blockIdx.x, rows, klo_tab, y, part_q);
+template <typename T, typename PH, int ND, bool FRAC, bool FIX>
+__global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restrict__ x, T* __restrict__ y,
+                                                     double* __restrict__ part_q) {
+  fp_body<T, PH, ND, FRAC, FIX>(P, blockIdx.x, blockIdx.x, x, y, part_q);
 }
 
 // ---------------------------------------------------------------------------
@@ -55,10 +50,10 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-template <typename T, int ND, bool FRAC, bool CG>
+template <typename T, typename PH, int ND, bool FRAC, bool CG>
 hipError_t launch_bp_t(const Plan& pl, const T* y, T* out, const CgArgs* cg, hipStream_t st) {
   const OpParams& P = pl.op;
-  auto kern = bp_kernel<T, ND, FRAC, CG>;
+  auto kern = bp_kernel<T, PH, ND, FRAC, CG>;
   hipError_t e = allow_lds(kern, pl.bp_lds);
   if (e != hipSuccess) return e;
   if (CG)
@@ -69,67 +64,69 @@ hipError_t launch_bp_t(const Plan& pl, const T* y, T* out, const CgArgs* cg, hip
   return hipGetLastError();
 }
 
-template <typename T, int ND, bool CG>
-hipError_t launch_bp_f(const Plan& pl, const T* y, T* out, const CgArgs* cg, hipStream_t st) {
-  return pl.op.t0f != 0.0f ? launch_bp_t<T, ND, true, CG>(pl, y, out, cg, st)
-                           : launch_bp_t<T, ND, false, CG>(pl, y, out, cg, st);
+template <typename T, typename PH, int ND>
+hipError_t launch_bp_f(const Plan& pl, const void* y, void* out, const CgArgs* cg, hipStream_t st) {
+  auto yy = static_cast<const T*>(y);
+  auto xx = static_cast<T*>(out);
+  const bool frac = pl.op.t0f != 0.0f;
+  if (cg) return frac ? launch_bp_t<T, PH, ND, true, true>(pl, yy, xx, cg, st) : launch_bp_t<T, PH, ND, false, true>(pl, yy, xx, cg, st);
+  return frac ? launch_bp_t<T, PH, ND, true, false>(pl, yy, xx, cg, st) : launch_bp_t<T, PH, ND, false, false>(pl, yy, xx, cg, st);
 }
 
-template <typename T, int ND, bool FRAC>
-hipError_t launch_fp_t(const Plan& pl, const T* x, T* rows, int* klo_tab, hipStream_t st) {
-  auto kern = fp_kernel<T, ND, FRAC>;
+template <typename T, typename PH, int ND, bool FRAC, bool FIX>
+hipError_t launch_fp_t(const Plan& pl, const T* x, T* y, double* part_q, hipStream_t st) {
+  auto kern = fp_kernel<T, PH, ND, FRAC, FIX>;
   hipError_t e = allow_lds(kern, pl.fp_lds);
   if (e != hipSuccess) return e;
-  kern<<<pl.fp_grid, kBlock, pl.fp_lds, st>>>(pl.op, x, rows, klo_tab);
+  kern<<<pl.fp_grid, kBlock, pl.fp_lds, st>>>(pl.op, x, y, part_q);
   return hipGetLastError();
 }
 
-template <typename T, int ND>
-hipError_t launch_fp_f(const Plan& pl, const T* x, T* rows, int* klo_tab, hipStream_t st) {
-  return pl.op.t0f != 0.0f ? launch_fp_t<T, ND, true>(pl, x, rows, klo_tab, st)
-                           : launch_fp_t<T, ND, false>(pl, x, rows, klo_tab, st);
+template <typename T, typename PH, int ND>
+hipError_t launch_fp_f(const Plan& pl, const void* x, void* y, double* part_q, hipStream_t st) {
+  auto xx = static_cast<const T*>(x);
+  auto yy = static_cast<T*>(y);
+  const bool frac = pl.op.t0f != 0.0f;
+  if constexpr (sizeof(PH) == 4) {
+    if (pl.op.ffix)
+      return frac ? launch_fp_t<T, PH, ND, true, true>(pl, xx, yy, part_q, st)
+                  : launch_fp_t<T, PH, ND, false, true>(pl, xx, yy, part_q, st);
+  }
+  return frac ? launch_fp_t<T, PH, ND, true, false>(pl, xx, yy, part_q, st)
+              : launch_fp_t<T, PH, ND, false, false>(pl, xx, yy, part_q, st);
 }
 
-template <typename T>
-hipError_t launch_forward_t(const Plan& pl, const T* x, T* y, void* scratch, double* part_q, hipStream_t st) {
-  unsigned char* sc = static_cast<unsigned char*>(scratch);
-  T* rows = reinterpret_cast<T*>(sc + pl.part_rows_off);
-  int* tab = reinterpret_cast<int*>(sc + pl.klo_tab_off);
-  hipError_t e = pl.ndim == 2 ? launch_fp_f<T, 2>(pl, x, rows, tab, st) : launch_fp_f<T, 3>(pl, x, rows, tab, st);
-  if (e != hipSuccess) return e;
-  auto g = fp_gather_kernel<T>;
-  if ((e = allow_lds(g, pl.gather_lds)) != hipSuccess) return e;
-  g<<<pl.gather_grid, kBlock, pl.gather_lds, st>>>(pl.op, rows, tab, y, part_q);
-  return hipGetLastError();
+template <typename T, typename PH>
+hipError_t launch_adj_d(const Plan& pl, const void* y, void* x, const CgArgs* cg, hipStream_t st) {
+  return pl.ndim == 2 ? launch_bp_f<T, PH, 2>(pl, y, x, cg, st) : launch_bp_f<T, PH, 3>(pl, y, x, cg, st);
+}
+
+template <typename T, typename PH>
+hipError_t launch_fwd_d(const Plan& pl, const void* x, void* y, double* part_q, hipStream_t st) {
+  return pl.ndim == 2 ? launch_fp_f<T, PH, 2>(pl, x, y, part_q, st) : launch_fp_f<T, PH, 3>(pl, x, y, part_q, st);
 }
 
 }  // namespace
 
 hipError_t launch_adjoint(const Plan& pl, const void* y, void* x, const CgArgs* cg, hipStream_t st) {
   if (pl.bp_grid == 0) return hipSuccess;
-  const bool CGm = cg != nullptr;
-  if (pl.dtype == PA_F32) {
-    auto yy = static_cast<const float*>(y);
-    auto xx = static_cast<float*>(x);
-    if (pl.ndim == 2) return CGm ? launch_bp_f<float, 2, true>(pl, yy, xx, cg, st) : launch_bp_f<float, 2, false>(pl, yy, xx, cg, st);
-    return CGm ? launch_bp_f<float, 3, true>(pl, yy, xx, cg, st) : launch_bp_f<float, 3, false>(pl, yy, xx, cg, st);
+  switch (pl.dtype) {
+    case PA_F32: return launch_adj_d<float, float>(pl, y, x, cg, st);
+    case PA_MIXED: return launch_adj_d<double, float>(pl, y, x, cg, st);
+    default: return launch_adj_d<double, double>(pl, y, x, cg, st);
   }
-  auto yy = static_cast<const double*>(y);
-  auto xx = static_cast<double*>(x);
-  if (pl.ndim == 2) return CGm ? launch_bp_f<double, 2, true>(pl, yy, xx, cg, st) : launch_bp_f<double, 2, false>(pl, yy, xx, cg, st);
-  return CGm ? launch_bp_f<double, 3, true>(pl, yy, xx, cg, st) : launch_bp_f<double, 3, false>(pl, yy, xx, cg, st);
 }
 
-hipError_t launch_forward(const Plan& pl, const void* x, void* y, void* scratch, double* part_q, hipStream_t st) {
-  if (pl.fp_grid == 0) {
-    // nothing to scatter: y = 0, ||y||^2 = 0
-    hipError_t e = launch_fill(pl.dtype, y, pl.M, st);
-    if (e != hipSuccess || !part_q) return e;
+hipError_t launch_forward(const Plan& pl, const void* x, void* y, double* part_q, hipStream_t st) {
+  if (pl.fp_grid == 0) {  // no samples: nothing to write, ||y||^2 = 0
+    if (!part_q) return hipSuccess;
     return launch_fill(PA_F64, part_q, 1, st);
   }
-  if (pl.dtype == PA_F32)
-    return launch_forward_t<float>(pl, static_cast<const float*>(x), static_cast<float*>(y), scratch, part_q, st);
-  return launch_forward_t<double>(pl, static_cast<const double*>(x), static_cast<double*>(y), scratch, part_q, st);
+  switch (pl.dtype) {
+    case PA_F32: return launch_fwd_d<float, float>(pl, x, y, part_q, st);
+    case PA_MIXED: return launch_fwd_d<double, float>(pl, x, y, part_q, st);
+    default: return launch_fwd_d<double, double>(pl, x, y, part_q, st);
+  }
 }
 
 }  // namespace pa

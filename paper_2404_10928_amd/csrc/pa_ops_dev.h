@@ -122,7 +122,7 @@ __device__ __forceinline__ void sensor_pos(const OpParams& P, int s, double sp[3
 // in the box [lo, hi] (sample units) for a sensor at sp.
 template <int ND>
 __device__ __forceinline__ int window_lo(const OpParams& P, const double lo[3], const double hi[3],
-                                         const double sp[3], bool* in_trace, int width) {
+                                         const double sp[3], bool* in_trace, int width, double* dmin_out = nullptr) {
   double dmin2 = 0.0, dmax2 = 0.0;
 #pragma unroll
   for (int a = 0; a < ND; ++a) {
@@ -133,6 +133,7 @@ __device__ __forceinline__ int window_lo(const OpParams& P, const double lo[3], 
   }
   double dmin = fmax(sqrt(dmin2), P.rmin);
   double dmax = fmax(sqrt(dmax2), P.rmin);
+  if (dmin_out) *dmin_out = dmin;
   double tmin = dmin - (double)P.t0i - P.t0fd;
   double tmax = dmax - (double)P.t0i - P.t0fd;
   *in_trace = tmax >= -2.0 && tmin <= (double)P.K + 1.0 && dmax < 4.0e6;
@@ -269,7 +270,33 @@ __device__ __forceinline__ T lds_load(const T* addr) {
       static_cast<unsigned>(reinterpret_cast<size_t>(addr)));
 }
 
-template <typename T> constexpr size_t near_bytes() { return sizeof(T) == 4 ? sizeof(Near32) : 0; }
+// floor(v + 0.5) as an int in one instruction (round half up; the two taps of
+// a pair are rounded the same way, so they still sum to the rounded total).
+__device__ __forceinline__ int round_i(float v) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
+// Sum over the 64 lanes of a wave with DPP moves (no LDS round trips), in a
+// fixed order; every lane gets the total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]: every lane holds its quad's sum
+  v += dpp_mov<0x124>(v);  // row_ror:4
+  v += dpp_mov<0x128>(v);  // row_ror:8: every lane holds its row's sum
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
+template <typename PH> constexpr size_t near_bytes() { return sizeof(PH) == 4 ? sizeof(Near32) : 0; }
 
 __device__ __forceinline__ bool is_near(const OpParams& P, const double ref[3], const double sp[3]) {
   const double dx = ref[0] - sp[0], dy = ref[1] - sp[1], dz = ref[2] - sp[2];
@@ -290,17 +317,17 @@ namespace {
 // few near sensors follow in an FP64-delay loop.
 // With CG the epilogue also performs x += alpha p, s = A^T r - lambda x and the
 // FP64 partial sums of ||s||^2 and ||x||^2.
-template <typename T, int ND, bool FRAC, bool CG>
+template <typename T, typename PH, int ND, bool FRAC, bool CG>
 __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, const T* __restrict__ y,
                                         T* __restrict__ out, T* __restrict__ xcg, const T* __restrict__ pcg,
                                         const double* __restrict__ alpha, double lambda,
                                         double* __restrict__ part_s, double* __restrict__ part_x) {
-  using SC = typename SCOf<T>::type;
-  using PX = typename PixOf<T>::type;
+  using SC = typename SCOf<PH>::type;
+  using PX = typename PixOf<PH>::type;
   constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
-  constexpr bool F32 = sizeof(T) == 4;
+  constexpr bool F32 = sizeof(PH) == 4;  // FP32 delay arithmetic (with the FP64 near path)
   extern __shared__ __align__(16) unsigned char smem[];
-  const BpLayout L = bp_layout(P.sc, P.wp, sizeof(T), sizeof(SC), near_bytes<T>());
+  const BpLayout L = bp_layout(P.sc, P.wp, sizeof(T), sizeof(SC), near_bytes<PH>());
   SC* sct = reinterpret_cast<SC*>(smem + L.sct);
   int* klo_s = reinterpret_cast<int*>(smem + L.klo);
   int* sid = reinterpret_cast<int*>(smem + L.sid);
@@ -410,7 +437,8 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
     int j = 0;
     for (; j + 4 <= nfar; j += 4) {
       int kb[4];
-      T f[4], wt[4], y0[4], y1[4];
+      PH f[4], wt[4];
+      T y0[4], y1[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) phase<ND, FRAC, (int)sizeof(T)>(sct[j + u], px, t0f, kb[u], f[u], wt[u]);
 #pragma unroll
@@ -420,16 +448,16 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
         y1[u] = lds_load(tap + 1);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = fma(wt[u], fma(f[u], y1[u] - y0[u], y0[u]), acc);
+      for (int u = 0; u < 4; ++u) acc = fma((T)wt[u], fma((T)f[u], y1[u] - y0[u], y0[u]), acc);
     }
     for (; j < nfar; ++j) {
       int kb;
-      T f, wt;
+      PH f, wt;
       phase<ND, FRAC, (int)sizeof(T)>(sct[j], px, t0f, kb, f, wt);
       const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
       const T y0 = lds_load(tap);
       const T y1 = lds_load(tap + 1);
-      acc = fma(wt, fma(f, y1 - y0, y0), acc);
+      acc = fma((T)wt, fma((T)f, y1 - y0, y0), acc);
     }
     if constexpr (F32) {
       if (nfar < nsc) {
@@ -439,11 +467,11 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
           const SC32& c = sct[j];
           int kb;
           float f, wt;
-          phase_near<ND, FRAC, 4>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, c.HALF, kb, f, wt);
-          const float* tap = reinterpret_cast<const float*>(static_cast<size_t>(kb));
-          const float y0 = lds_load(tap);
-          const float y1 = lds_load(tap + 1);
-          acc = fmaf(wt, fmaf(f, y1 - y0, y0), acc);
+          phase_near<ND, FRAC, (int)sizeof(T)>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, c.HALF, kb, f, wt);
+          const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
+          const T y0 = lds_load(tap);
+          const T y1 = lds_load(tap + 1);
+          acc = fma((T)wt, fma((T)f, y1 - y0, y0), acc);
         }
       }
     }
@@ -451,7 +479,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
   }
 
   const size_t idx = ((size_t)iz * P.ny + iy) * P.nx + ix;
-  const T scale = F32 ? (T)P.out_scale : (T)P.out_scale_d;
+  const T scale = F32 ? (sizeof(T) == 4 ? (T)P.out_scale : (T)P.out_scale_h) : (T)P.out_scale_d;
   if (!CG) {
     if (valid) out[idx] = acc * scale;
     return;
@@ -477,302 +505,290 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
 }
 
 // ---------------------------------------------------------------------------
-// A, pass 1: one work-group per (forward tile, chunk of 64 sensors); lane =
-// sensor, wave w walks base tiles w, w+4, ... of the forward tile (or, with
-// fewer than four base tiles, a quarter or half of one) one pixel at a time
-// (the pixel is uniform across the wave).  Each lane scatters its two
-// taps into its own sensor's LDS histogram row, so the lanes of one ds_add
-// never collide on an address.  The rows are then written out with plain
-// coalesced stores, with the first sample of each row in a table.
-template <typename T, int ND, bool FRAC>
-__device__ __forceinline__ void fp_body(const OpParams& P, int b, const T* __restrict__ x, T* __restrict__ rows,
-                                        int* __restrict__ klo_tab) {
-  using SC = typename SCOf<T>::type;
-  using PX = typename PixOf<T>::type;
+// A: one work-group per (sensor s, segment of fseg samples of its trace), one
+// pixel per lane and four pixels per lane per base tile.  The work-group owns
+// its outputs, so no partial rows leave it and no other work-group adds into
+// them.
+//
+// Rounds of kFwdList base tiles: every lane tests one tile's window against
+// the segment (plus a window's margin, since a tile reaching the segment may
+// also reach its neighbours) and the tiles that reach it are compacted into
+// an LDS list, in tile order, with their per-(tile, sensor) constants.  Wave w
+// then takes groups of kFwdGroup consecutive list entries, groups w, w+4, ...:
+// the sensor and tiles are uniform across the wave, so the delay constants
+// are wave-uniform LDS reads, and each lane keeps its four pixels' offsets
+// from a tile centre in registers for the whole kernel.  The next group's x
+// values are loaded while the current group is processed.
+//
+// Bins, FP32 delay arithmetic (PA_F32, PA_MIXED), by default: the taps of a
+// group go to a wave-private row of 32-bit fixed-point bins (LDS integer adds
+// are fast on gfx950 and their sums do not depend on order), scaled by
+// 2^30 / B with B = sum over the group's tiles of (sum of |x| over the tile)
+// / (2 dmin), a bound on every partial sum of a bin; the touched part of the
+// row is then added, in FP64, into the wave's histogram and cleared.
+// Otherwise (PA_F64, or FP64 bins chosen for FP32 delay arithmetic) taps go
+// straight into the wave's FP64 histogram with LDS FP64 adds.  Either way
+// each wave adds its tiles in list order and the four waves' histograms are
+// summed in a fixed order, so y is the same on every run.
+// A non-finite x in a group makes its bound non-finite (fixed-point rows) or
+// its taps non-finite (FP64 bins), so non-finite inputs give non-finite traces.
+template <typename T, typename PH, int ND, bool FRAC, bool FIX>
+__device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, const T* __restrict__ x,
+                                        T* __restrict__ y, double* __restrict__ part_q) {
+  using SC = typename SCOf<PH>::type;
+  using PX = typename PixOf<PH>::type;
   constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
-  constexpr int NS = kSensorsPerFwdBlock;
-  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int PPL = TX * TY * TZ / 64;   // pixels per lane per base tile
+  constexpr int G = kFwdGroup;
+  constexpr bool P32 = sizeof(PH) == 4;
+  constexpr int HB = FIX ? 4 : 8;          // bytes per bin of the rows the taps go to
+  static_assert(P32 || !FIX, "fixed-point rows are for FP32 delay arithmetic");
   extern __shared__ __align__(16) unsigned char smem[];
-  const FpLayout L = fp_layout(P.wpa, P.nsub, sizeof(T), sizeof(PX));
-  // Histogram bins.  FP64 kernels add doubles.  FP32 kernels add 32-bit
-  // fixed-point integers (LDS float adds are slow on gfx950, integer adds are
-  // not): lane s scales its taps by 2^30 / B_s, where B_s bounds the sum of
-  // |tap| over the whole forward tile, so no bin can overflow; integer sums
-  // do not depend on their order, and each row is converted back once, when
-  // it is written out.
-  using H = typename std::conditional<F32, int, double>::type;
-  constexpr int HB = (int)sizeof(H);
-  H* hist = reinterpret_cast<H*>(smem + L.hist);
-  PX* pixtab = reinterpret_cast<PX*>(smem + L.pixtab);
-  T* xs = reinterpret_cast<T*>(smem + L.xs);
-  int* klo_a = reinterpret_cast<int*>(smem + L.klo);
-  double* inv_a = reinterpret_cast<double*>(smem + L.inv);
+  const FpLayout L = fp_layout(P.fbins, P.wp, sizeof(SC), FIX);
+  SC* lst = reinterpret_cast<SC*>(smem + L.lst);
+  FpTile* ltab = reinterpret_cast<FpTile*>(smem + L.ltab);
   __shared__ double red[4];
+  __shared__ int cnt[4];
 
-  const int chunk = b % P.n_chunks;
-  const int at = b / P.n_chunks;
-  const int ax = at % P.natile[0];
-  const int ay = (at / P.natile[0]) % P.natile[1];
-  const int az = at / (P.natile[0] * P.natile[1]);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
-  const int s = chunk * NS + lane;
-  const bool s_ok = s < P.S;
-
-  // pixel offsets of a base tile (same for every base tile) and the forward tile's x values
-  {
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    make_pix<ND>(P, lx, ly, lz, pixtab[tid]);
-    for (int m = 0; m < P.nsub; ++m) {
-      const int bx = ax * P.msub[0] + m % P.msub[0];
-      const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
-      const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
-      const int ix = bx * TX + lx, iy = by * TY + ly, iz = bz * TZ + lz;
-      T v = 0;
-      if (ix < P.nx && iy < P.ny && iz < P.nz) v = x[((size_t)iz * P.ny + iy) * P.nx + ix];
-      xs[m * kBlock + tid] = v;
-    }
-  }
-  // this lane's sensor and its window over the whole forward tile
-  double sp[3];
-  sensor_pos<ND>(P, s_ok ? s : P.S - 1, sp);
-  bool in_trace;
-  int kl;
-  {
-    double lo[3], hi[3];
-    const int T3[3] = {TX, TY, TZ};
-    double r0[3];
-    tile_ref<ND>(P, ax * P.msub[0], ay * P.msub[1], az * P.msub[2], r0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
-      hi[a] = lo[a] + (P.msub[a] * T3[a] - 1) * P.hs;
-    }
-    if (ND == 2) { lo[2] = 0.0; hi[2] = 0.0; }
-    kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wpa);
-  }
-  const bool active = s_ok && in_trace;
-  // Fixed-point scale: a tap of pixel p in base tile m is at most
-  // |x_p| / (2 dmin_m), dmin_m being the distance from this lane's sensor to
-  // base tile m (clamped at r_min), so B_s = sum_m (sum_{p in m} |x_p|) /
-  // (2 dmin_m) bounds every partial sum of the row.
-  float scl = 0.f;
-  if constexpr (F32) {
-    double* sa_m = reinterpret_cast<double*>(smem + L.inv) + NS;  // [nsub][4] per-wave partials
-    for (int m = 0; m < P.nsub; ++m) {
-      double v = fabs((double)xs[m * kBlock + tid]);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (lane == 0) sa_m[m * 4 + wave] = v;
-    }
-    __syncthreads();
-    double bound = 0.0;
-    for (int m = 0; m < P.nsub; ++m) {
-      const double sa = (sa_m[m * 4 + 0] + sa_m[m * 4 + 1]) + (sa_m[m * 4 + 2] + sa_m[m * 4 + 3]);
-      if (sa == 0.0) continue;
-      const int bx = ax * P.msub[0] + m % P.msub[0];
-      const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
-      const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
-      double r0[3], lo[3], hi[3];
-      tile_ref<ND>(P, bx, by, bz, r0);
-      const int T3[3] = {TX, TY, TZ};
-      double d2 = 0.0;
-#pragma unroll
-      for (int a = 0; a < ND; ++a) {
-        lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
-        hi[a] = r0[a] + 0.5 * (T3[a] - 1) * P.hs;
-        const double e = fmax(fmax(lo[a] - sp[a], sp[a] - hi[a]), 0.0);
-        d2 += e * e;
-      }
-      bound += sa * (0.5 / fmax(sqrt(d2), P.rmin));
-    }
-    bound *= 1.0 + 1.0 / 1024.0;
-    if (bound > 0.0 && bound < 1e300) scl = (float)(1073741824.0 / bound);
-    if (wave == 0) inv_a[lane] = scl > 0.f ? 1.0 / (double)scl : 0.0;
-  }
-  if (wave == 0) klo_a[lane] = active ? kl : P.K + 8;
-  for (int e = tid; e < NS * P.wpa; e += kBlock) hist[e] = 0;
-  __syncthreads();
-
-  const float t0f = P.t0f;
-  // Work items: (base tile m, part).  With fewer than four base tiles per
-  // forward tile the waves split each tile's pixels into `parts` ranges.
-  const int parts = P.nsub >= 4 ? 1 : 4 / P.nsub;
-  for (int item = wave; item < P.nsub * parts; item += 4) {
-    const int m = item / parts;
-    const int part = item - m * parts;
-    const int bx = ax * P.msub[0] + m % P.msub[0];
-    const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
-    const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
-    const int nlx = __builtin_amdgcn_readfirstlane(min(TX, P.nx - bx * TX));
-    const int nly = __builtin_amdgcn_readfirstlane(min(TY, P.ny - by * TY));
-    const int nlz = __builtin_amdgcn_readfirstlane(min(TZ, P.nz - bz * TZ));
-    if (nlx <= 0 || nly <= 0 || nlz <= 0) continue;
-    double ref[3];
-    tile_ref<ND>(P, bx, by, bz, ref);
-    // Near (tile, sensor) pairs take benign zero-weight constants here and
-    // are added afterwards, one sensor at a time with one pixel per lane, so
-    // the wave never runs the FP64 delay path for all of its pixels.
-    const bool near = F32 && active && is_near(P, ref, sp);
-    SC c;
-    make_sc<ND>(P, ref, sp, kl, lane * P.wpa, HB, active && !near, c);
-    c.BASE += (int)(size_t)hist;  // absolute LDS byte address
-    asm volatile("" : "+v"(c.BASE));  // keep "k * HB + BASE" a single shift-add
-    const T* xm = xs + m * kBlock;
-    // Every pixel of the base tile, in order.  Pixels beyond the image edge
-    // have x = 0 (and taps inside the window), so they add zeros.  The next
-    // pixel's constants are read before this pixel's LDS adds are issued, so
-    // the adds never hold up the reads.
-    constexpr int NPIX = TX * TY * TZ;
-    const int p_lo = part * (NPIX / parts);
-    const int p_hi = p_lo + NPIX / parts;
-    PX pn = pixtab[p_lo];
-    T xn = xm[p_lo];
-#pragma unroll 2
-    for (int p = p_lo; p < p_hi; ++p) {
-      const PX px = pn;
-      const T xp = xn;
-      const int pq = p + 1 < p_hi ? p + 1 : p;
-      pn = pixtab[pq];
-      xn = xm[pq];
-      int kb;
-      T f, wt;
-      phase<ND, FRAC, HB, false>(c, px, t0f, kb, f, wt);
-      H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
-      if constexpr (F32) {
-        const float vs = (wt * xp) * scl;
-        const int it = (int)__builtin_rintf(vs);
-        const int i1 = (int)__builtin_rintf(vs * f);
-        lds_add(bin, it - i1);
-        lds_add(bin + 1, i1);
-      } else {
-        const double v = wt * xp;
-        const double a1 = v * f;
-        lds_add(bin, v - a1);
-        lds_add(bin + 1, a1);
-      }
-    }
-    if constexpr (F32) {
-      uint64_t nm = part == 0 ? __ballot(near) : 0;  // the near pairs of tile m, once
-      if (nm != 0) {
-        const double rmin2 = P.rmin * P.rmin;
-        // this lane's row base for its own sensor, as the far constants would have it
-        const double kr_l = rint(sqrt((ref[0] - sp[0]) * (ref[0] - sp[0]) + (ref[1] - sp[1]) * (ref[1] - sp[1]) +
-                                      (ref[2] - sp[2]) * (ref[2] - sp[2])));
-        const int base_l = ((int)kr_l - P.t0i - kl + lane * P.wpa) * HB + (int)(size_t)hist;
-        while (nm != 0) {
-          const int j = __builtin_ctzll(nm);
-          nm &= nm - 1;
-          Near32 nn;
-          nn.DX = ref[0] - __shfl(sp[0], j);
-          nn.DY = ref[1] - __shfl(sp[1], j);
-          nn.DZ = ref[2] - __shfl(sp[2], j);
-          nn.KR = __shfl(kr_l, j);
-          const int base = __shfl(base_l, j);
-          const float scl_j = __shfl(scl, j);
-          for (int pix = lane; pix < TX * TY * TZ; pix += 64) {
-            const int lx = pix % TX, ly = (pix / TX) % TY, lz = pix / (TX * TY);
-            if (lx >= nlx || ly >= nly || lz >= nlz) continue;
-            double o[3];
-            pix_offsets<ND>(P, lx, ly, lz, o);
-            int kb;
-            float f, wt;
-            phase_near<ND, FRAC, HB>(nn, o, rmin2, P.t0fd, base, 0.5f, kb, f, wt);
-            const float vs = (wt * xm[pix]) * scl_j;
-            const int it = (int)__builtin_rintf(vs);
-            const int i1 = (int)__builtin_rintf(vs * f);
-            H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
-            lds_add(bin, it - i1);
-            lds_add(bin + 1, i1);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // histogram rows out, row (sensor, forward tile) at ((s * n_atiles) + at) * wpa
-  for (int j = wave; j < NS; j += 4) {
-    const int sj = chunk * NS + j;
-    if (sj >= P.S) break;
-    T* row = rows + ((size_t)sj * P.n_atiles + at) * P.wpa;
-    if constexpr (F32) {
-      const double inv = inv_a[j];
-      for (int i = lane; i < P.wpa; i += 64) row[i] = (T)((double)hist[j * P.wpa + i] * inv);
-    } else {
-      for (int i = lane; i < P.wpa; i += 64) row[i] = (T)hist[j * P.wpa + i];
-    }
-  }
-  if (wave == 0 && s_ok) klo_tab[(size_t)s * P.n_atiles + at] = klo_a[lane];
-}
-
-// A, pass 2: one work-group per (sensor, segment of kseg <= 256 samples),
-// one sample per lane.  Each wave scans the window starts of the sensor's
-// forward tiles, 64 at a time, picks by ballot the tiles whose row window
-// overlaps its own 64 samples, and every lane adds its sample of those rows,
-// in increasing tile order, in FP64 (kGatherLoads loads in flight, the next 64
-// window starts prefetched); then the work-group scales, writes y and forms
-// the FP64 partial of ||y||^2.  No atomics: the result is the same on every
-// run.  Rows and window starts are sensor-major, so one sensor's rows are
-// contiguous.
-constexpr int kGatherLoads = 16;
-
-template <typename T>
-__device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx, const T* __restrict__ rows,
-                                            const int* __restrict__ klo_tab, T* __restrict__ y,
-                                            double* __restrict__ part_q) {
-  __shared__ double red[4];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int s = blk / P.nseg;
-  const int seg = blk - s * P.nseg;
-  const int k0 = seg * P.kseg;
-  const int kn = min(P.kseg, P.K - k0);
-  const int k = k0 + tid;
-  const bool k_ok = tid < kn;
-  const int* kt = klo_tab + (size_t)s * P.n_atiles;
-  const T* srow = rows + (size_t)s * P.n_atiles * P.wpa;
-  const int wlo = k0 + wave * 64, whi = min(k0 + kn, wlo + 64);  // this wave's samples
-  double acc = 0.0;
-  if (wlo < whi) {
-    // window starts of the next 64 tiles are loaded while this chunk's rows are read
-    int kl_next = lane < P.n_atiles ? kt[lane] : 0;
-    for (int c0 = 0; c0 < P.n_atiles; c0 += 64) {
-      const int t = c0 + lane;
-      const int kl = kl_next;
-      const bool ov = t < P.n_atiles && kl < whi && kl + P.wpa > wlo;
-      if (t + 64 < P.n_atiles) kl_next = kt[t + 64];
-      uint64_t m = __ballot(ov);
-      while (m != 0) {
-        double v[kGatherLoads];
+  const int s = b / P.fnseg;
+  const int k0 = (b - s * P.fnseg) * P.fseg;   // first sample of this work-group's segment
+  const int hlo = k0 - P.wp - 1;               // sample of histogram bin 0
+  double* hist = reinterpret_cast<double*>(smem + L.hist) + wave * P.fbins;
+  int* irow = reinterpret_cast<int*>(smem + L.irow + (size_t)wave * align16((size_t)P.fbins * 4));
+  for (int e = lane; e < P.fbins; e += 64) {
+    hist[e] = 0.0;
+    if constexpr (FIX) irow[e] = 0;
+  }
+  const int rbase = FIX ? (int)(size_t)irow : (int)(size_t)hist;  // LDS byte address of this wave's tap row
+  double sp[3];
+  sensor_pos<ND>(P, s, sp);
+  // this lane's pixels of a base tile: p = lane + 64 q
+  PX px[PPL];
+  int poff[PPL], plim[PPL];
 #pragma unroll
-        for (int u = 0; u < kGatherLoads; ++u) {
-          v[u] = 0.0;
-          if (m != 0) {  // wave-uniform
-            const int b = __builtin_ctzll(m);
-            m &= m - 1;
-            const int klb = __builtin_amdgcn_readlane(kl, b);
-            const int j = k - klb;
-            if (k_ok && j >= 0 && j < P.wpa) v[u] = (double)srow[(size_t)(c0 + b) * P.wpa + j];
+  for (int q = 0; q < PPL; ++q) {
+    const int p = lane + 64 * q;
+    const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+    make_pix<ND>(P, lx, ly, lz, px[q]);
+    poff[q] = (lz * P.ny + ly) * P.nx + lx;
+    plim[q] = lx | ly << 8 | lz << 16;
+  }
+  const float t0f = P.t0f;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  constexpr int kFull = TX | TY << 8 | TZ << 16;  // FpTile::lim of a tile inside the image
+
+  for (int c0 = 0; c0 < P.n_tiles; c0 += kFwdList) {
+    // ---- list the tiles of this round whose window reaches the segment
+    const int t = c0 + tid;
+    bool take = false;
+    int kl = 0;
+    double ref[3], dmin = 0.0;
+    int bx = 0, by = 0, bz = 0;
+    if (t < P.n_tiles) {
+      bx = t % P.ntile[0];
+      by = (t / P.ntile[0]) % P.ntile[1];
+      bz = t / (P.ntile[0] * P.ntile[1]);
+      tile_ref<ND>(P, bx, by, bz, ref);
+      double lo[3], hi[3];
+      const int T3[3] = {TX, TY, TZ};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double half = 0.5 * (T3[a] - 1) * P.hs;
+        lo[a] = ref[a] - half;
+        hi[a] = ref[a] + half;
+      }
+      bool in_trace = false;
+      kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wp, &dmin);
+      take = in_trace && kl < k0 + P.fseg && kl + P.wp > k0;
+    }
+    const unsigned long long bal = __ballot(take);
+    __syncthreads();  // the previous round's list has been consumed
+    if (lane == 0) cnt[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += cnt[w];
+    const int nl = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    if (take) {
+      const int pos = before + __popcll(bal & lt_mask);
+      SC c;
+      make_sc<ND>(P, ref, sp, hlo, 0, HB, true, c);  // tap bins relative to the histogram
+      lst[pos] = c;
+      FpTile ft;
+      ft.tile = t;
+      ft.off = kl - hlo;
+      ft.xoff = ((bz * TZ) * P.ny + by * TY) * P.nx + bx * TX;
+      ft.lim = min(TX, P.nx - bx * TX) | min(TY, P.ny - by * TY) << 8 | min(TZ, P.nz - bz * TZ) << 16;
+      ft.ib = (float)(0.5 / dmin);
+      ft.near = (P32 && is_near(P, ref, sp)) ? 1 : 0;
+      ft.pad[0] = ft.pad[1] = 0;
+      ltab[pos] = ft;
+    }
+    __syncthreads();
+
+    // ---- scatter: wave w takes groups w, w+4, ... of G consecutive entries
+    const int ngroups = (nl + G - 1) / G;
+    T xn[G][PPL];
+    auto load_x = [&](int g0, T (&xv)[G][PPL]) {
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int j = g0 * G + u;
+        const int xoff = __builtin_amdgcn_readfirstlane(j < nl ? ltab[j].xoff : 0);
+        const int lim = __builtin_amdgcn_readfirstlane(j < nl ? ltab[j].lim : 0);
+        const T* __restrict__ xb = x + xoff;   // wave-uniform base, per-lane 32-bit offsets
+        if (lim == kFull) {
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) xv[u][q] = xb[(unsigned)poff[q]];
+        } else {  // a tile at the image edge (or past the list's end: lim = 0)
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) {
+            const bool in = (plim[q] & 0xff) < (lim & 0xff) && ((plim[q] >> 8) & 0xff) < ((lim >> 8) & 0xff) &&
+                            (plim[q] >> 16) < (lim >> 16);
+            xv[u][q] = in ? xb[(unsigned)poff[q]] : (T)0;
           }
         }
+      }
+    };
+    if (wave < ngroups) load_x(wave, xn);
+    for (int gi = wave; gi < ngroups; gi += 4) {
+      T xv[G][PPL];
 #pragma unroll
-        for (int u = 0; u < kGatherLoads; ++u) acc += v[u];
+      for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) xv[u][q] = xn[u][q];
+      if (gi + 4 < ngroups) load_x(gi + 4, xn);
+      const int j0 = gi * G;
+      const int nu = min(G, nl - j0);
+      float scl = 0.f;
+      double inv = 0.0;
+      int rlo = 0, rhi = 0;   // bins of the int row this group touches
+      if constexpr (FIX) {
+        // the group's bound and fixed-point scale
+        float sa = 0.f;
+        rlo = P.fbins;
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          if (u < nu) {
+            const float ib = ltab[j0 + u].ib;
+            const int off = __builtin_amdgcn_readfirstlane(ltab[j0 + u].off);
+            float su = 0.f;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) su += fabsf((float)xv[u][q]);
+            sa = fmaf(su, ib, sa);
+            rlo = min(rlo, off);
+            rhi = max(rhi, off + P.wp);
+          }
+        }
+        const float bound = wave_sum(sa) * (1.0f + 1.0f / 256.0f);
+        // (the kernels are built without NaN semantics, so non-finite values
+        // are recognised from their exponent bits)
+        if ((__float_as_uint(bound) & 0x7f800000u) == 0x7f800000u) {
+          for (int e = rlo + lane; e < rhi; e += 64) hist[e] = __uint_as_float(0x7fc00000u);
+          continue;  // a NaN or infinite x (or a sum beyond float): the group's windows become NaN
+        }
+        if (bound == 0.0f) continue;  // all-zero tiles: nothing to add
+        scl = 1073741824.0f * __builtin_amdgcn_rcpf(bound);
+        inv = 1.0 / (double)scl;
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        if (u >= nu) break;
+        SC c = lst[j0 + u];
+        c.BASE += rbase;
+        const int near = __builtin_amdgcn_readfirstlane(ltab[j0 + u].near);
+        if (!P32 || near == 0) {
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) {
+            int kb;
+            PH f, wt;
+            phase<ND, FRAC, HB, false>(c, px[q], t0f, kb, f, wt);
+            if constexpr (FIX) {
+              const float vs = (wt * (float)xv[u][q]) * scl;
+              const int it = round_i(vs);
+              const int i1 = round_i(vs * f);
+              int* bin = reinterpret_cast<int*>(static_cast<size_t>(kb));
+              lds_add(bin, it - i1);
+              lds_add(bin + 1, i1);
+            } else {
+              const double v = (double)wt * (double)xv[u][q];
+              const double a1 = v * (double)f;
+              double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
+              lds_add(bin, v - a1);
+              lds_add(bin + 1, a1);
+            }
+          }
+        } else if constexpr (P32) {
+          // sensor among or near the tile's pixels: delays from FP64 coordinates
+          const int tb = ltab[j0 + u].tile;
+          double rf[3];
+          tile_ref<ND>(P, tb % P.ntile[0], (tb / P.ntile[0]) % P.ntile[1], tb / (P.ntile[0] * P.ntile[1]), rf);
+          Near32 nn;
+          nn.DX = rf[0] - sp[0];
+          nn.DY = rf[1] - sp[1];
+          nn.DZ = rf[2] - sp[2];
+          nn.KR = rint(sqrt(nn.DX * nn.DX + nn.DY * nn.DY + nn.DZ * nn.DZ));
+          const double rmin2 = P.rmin * P.rmin;
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) {
+            const int p = lane + 64 * q;
+            double o[3];
+            pix_offsets<ND>(P, p % TX, (p / TX) % TY, p / (TX * TY), o);
+            int kb;
+            float f, wt;
+            phase_near<ND, FRAC, HB>(nn, o, rmin2, P.t0fd, c.BASE, 0.5f, kb, f, wt);
+            if constexpr (FIX) {
+              const float vs = (wt * (float)xv[u][q]) * scl;
+              const int it = round_i(vs);
+              const int i1 = round_i(vs * f);
+              int* bin = reinterpret_cast<int*>(static_cast<size_t>(kb));
+              lds_add(bin, it - i1);
+              lds_add(bin + 1, i1);
+            } else {
+              const double v = (double)wt * (double)xv[u][q];
+              const double a1 = v * (double)f;
+              double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
+              lds_add(bin, v - a1);
+              lds_add(bin + 1, a1);
+            }
+          }
+        }
+      }
+      if constexpr (FIX) {
+        // the touched bins into the histogram (this wave's own bins: plain LDS
+        // reads and writes, each lane its own), then cleared for the next group
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int e = rlo + lane; e < rhi; e += 64) {
+          const int v = irow[e];
+          if (v != 0) {
+            hist[e] += (double)v * inv;
+            irow[e] = 0;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
       }
     }
   }
-  const double scale = sizeof(T) == 4 ? 2.0 * P.inv_cdt : P.out_scale_d;
-  double q = 0.0;
-  if (k_ok) {
-    const T out = (T)(acc * scale);
-    y[(size_t)s * P.K + k] = out;
-    q = (double)out * (double)out;
+  __syncthreads();
+
+  // ---- the segment out: the four waves' histograms in a fixed order
+  const double* h0 = reinterpret_cast<const double*>(smem + L.hist);
+  const double scale = P32 ? P.out_scale_h : P.out_scale_d;
+  const int kn = min(P.fseg, P.K - k0);
+  double qq = 0.0;
+  for (int i = tid; i < kn; i += kBlock) {
+    const int e = i + P.wp + 1;
+    const double v = (h0[e] + h0[P.fbins + e]) + (h0[2 * P.fbins + e] + h0[3 * P.fbins + e]);
+    const T out = (T)(v * scale);
+    y[(size_t)s * P.K + k0 + i] = out;
+    qq += (double)out * (double)out;
   }
   if (part_q) {
-    q = block_sum(q, red);
-    if (tid == 0) part_q[pidx] = q;
+    qq = block_sum(qq, red);
+    if (tid == 0) part_q[pidx] = qq;
   }
 }
 

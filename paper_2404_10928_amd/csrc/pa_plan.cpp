@@ -43,6 +43,7 @@ struct TuneKey {
 
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuning>* g_tune = nullptr;
+uint64_t g_tune_epoch = 0;   // bumped whenever the table changes
 
 TuneKey tune_key(const pa_geometry* g, pa_dtype dtype) {
   TuneKey k{g->ndim, (int32_t)dtype, g->nx, g->ny, g->nz, g->n_sensors, g->n_samples, 0};
@@ -57,6 +58,7 @@ void tune_store(const pa_geometry* g, pa_dtype dtype, const Tuning& t) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (!g_tune) g_tune = new std::map<TuneKey, Tuning>();
   (*g_tune)[tune_key(g, dtype)] = t;
+  ++g_tune_epoch;
 }
 
 bool tune_lookup(const pa_geometry* g, pa_dtype dtype, Tuning* t) {
@@ -71,15 +73,18 @@ bool tune_lookup(const pa_geometry* g, pa_dtype dtype, Tuning* t) {
 void tune_clear() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (g_tune) g_tune->clear();
+  ++g_tune_epoch;
 }
 
-int fwd_tile_candidates(int ndim, int (*out)[3], int max) {
-  static const int c2[][3] = {{1, 1, 1}, {2, 1, 1}, {2, 2, 1}, {4, 2, 1}, {4, 4, 1}};
-  static const int c3[][3] = {{1, 1, 1}, {2, 1, 2}, {2, 2, 2}, {2, 2, 4}, {4, 2, 4}};
-  const int (*c)[3] = ndim == 2 ? c2 : c3;
-  const int n = std::min(5, max);
-  for (int i = 0; i < n; ++i)
-    for (int a = 0; a < 3; ++a) out[i][a] = c[i][a];
+uint64_t tune_epoch() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune_epoch;
+}
+
+int fwd_seg_candidates(int32_t* out, int max) {
+  static const int32_t c[] = {128, 256, 512, 1024};
+  const int n = std::min(4, max);
+  for (int i = 0; i < n; ++i) out[i] = c[i];
   return n;
 }
 
@@ -93,7 +98,8 @@ int adj_lds_candidates(size_t* out, int max) {
 pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::string* msg, const Tuning* force) {
   if (!g) return fail(msg, PA_ERR_INVALID_ARGUMENT, "geometry pointer is NULL");
   if (!plan) return fail(msg, PA_ERR_INVALID_ARGUMENT, "plan pointer is NULL");
-  if (dtype != PA_F32 && dtype != PA_F64) return fail(msg, PA_ERR_INVALID_ARGUMENT, "dtype must be PA_F32 or PA_F64");
+  if (dtype != PA_F32 && dtype != PA_F64 && dtype != PA_MIXED)
+    return fail(msg, PA_ERR_INVALID_ARGUMENT, "dtype must be PA_F32, PA_F64 or PA_MIXED");
   if (g->ndim != 2 && g->ndim != 3) return fail(msg, PA_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
   if (g->nx < 0 || g->ny < 0 || g->nz < 0) return fail(msg, PA_ERR_INVALID_ARGUMENT, "image sizes must be >= 0");
   if (g->ndim == 2 && g->nz != 1) return fail(msg, PA_ERR_INVALID_ARGUMENT, "nz must be 1 for a 2D geometry");
@@ -109,7 +115,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   if (g->sensors && (reinterpret_cast<uintptr_t>(g->sensors) % 8) != 0)
     return fail(msg, PA_ERR_INVALID_ARGUMENT, "sensors must be 8-byte aligned");
 
-  Tuning tuned{{0, 0, 0}, 0};
+  Tuning tuned{0, 0, 0};
   if (force) tuned = *force;
   else (void)tune_lookup(g, dtype, &tuned);
 
@@ -129,7 +135,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   pl = Plan{};
   pl.ndim = g->ndim;
   pl.dtype = dtype;
-  pl.elem = dtype == PA_F32 ? 4 : 8;
+  pl.elem = data_is_f32(dtype) ? 4 : 8;
   pl.P = P;
   pl.M = M;
   OpParams& op = pl.op;
@@ -168,10 +174,9 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   op.n_tiles = op.ntile[0] * op.ntile[1] * op.ntile[2];
 
   const size_t elem = pl.elem;
-  const bool f32 = dtype == PA_F32;
-  const size_t sc_bytes = f32 ? 48 : 64;     // per-sensor constants in LDS (adjoint)
-  const size_t near_bytes = f32 ? 32 : 0;    // FP64 sensor vector + reference (FP32 near path)
-  const size_t pix_bytes = f32 ? 16 : 32;
+  const bool p32 = phase_is_f32(dtype);
+  const size_t sc_bytes = p32 ? 48 : 64;     // per-(tile, sensor) constants in LDS
+  const size_t near_bytes = p32 ? 32 : 0;    // FP64 sensor vector + reference (FP32 near path)
 
   // Sensors closer than three base-tile half-diagonals to a tile centre take
   // the FP64 delay path in the FP32 kernels (the tile-local FP32 form loses
@@ -208,85 +213,55 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     if (pl.bp_lds > kLdsMax) return fail(msg, PA_ERR_UNSUPPORTED, "adjoint LDS plan exceeds 160 KiB");
   }
 
-  // Forward: histogram window of one sensor over a forward tile made of
-  // msub base tiles.  Prefer the largest forward tile (fewest partial rows)
-  // whose LDS keeps several work-groups per CU; else the largest that fits.
+  // Forward: one work-group per (sensor, segment of fseg samples).  It lists
+  // the base tiles whose window reaches its segment and scatters their
+  // pixels' taps into one FP64 histogram per wave covering the segment plus
+  // a window's margin on either side.  The segment is the tuned one, else
+  // the longest of 1024, 512, 256 and 128 samples that still gives at least
+  // 1024 work-groups (four per CU), and never more than the trace.
   {
-    int cand2[2][3] = {{2, 2, 1}, {1, 1, 1}};
-    int cand3[4][3] = {{2, 2, 4}, {2, 2, 2}, {2, 1, 2}, {1, 1, 1}};
-    int (*cand)[3] = nd == 2 ? cand2 : cand3;
-    const int ncand = nd == 2 ? 2 : 4;
-    bool ok = false;
-    if (tuned.fwd_tile[0] > 0 && tuned.fwd_tile[1] > 0 && tuned.fwd_tile[2] > 0) {
-      const int* m = tuned.fwd_tile;
-      const bool shape_ok = nd == 3 || m[2] == 1;
-      double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
-      double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
-      if (shape_ok && diag <= 1e6) {
-        int32_t wpa = ((int32_t)std::ceil(diag) + 5) | 1;
-        int nsub = m[0] * m[1] * m[2];
-        size_t lds = fp_layout(wpa, nsub, elem, pix_bytes).total;
-        if (lds <= kLdsMax) {
-          for (int a = 0; a < 3; ++a) op.msub[a] = m[a];
-          op.nsub = nsub;
-          op.wpa = wpa;
-          pl.fp_lds = lds;
-          ok = true;
-        }
+    op.ffix = p32 && tuned.fwd_mode != 2 ? 1 : 0;
+    const bool fix = op.ffix != 0;
+    auto bins = [&](int32_t seg) { return seg + 2 * op.wp + 2; };
+    auto fits = [&](int32_t seg) { return fp_layout(bins(seg), op.wp, sc_bytes, fix).total <= kLdsMax; };
+    const int64_t Kp = std::max<int64_t>(g->n_samples, 1);
+    int32_t seg = 0;
+    if (tuned.fwd_seg > 0 && fits(tuned.fwd_seg)) seg = tuned.fwd_seg;
+    if (seg == 0) {
+      int32_t cand[4];
+      const int nc = fwd_seg_candidates(cand, 4);
+      for (int i = nc - 1; i >= 0 && seg == 0; --i) {
+        const int64_t wg = (int64_t)g->n_sensors * ((Kp + cand[i] - 1) / cand[i]);
+        if ((wg >= 1024 || i == 0) && fits(cand[i])) seg = cand[i];
       }
+      for (int i = 0; i < nc && seg == 0; ++i)
+        if (fits(cand[i])) seg = cand[i];
     }
-    for (size_t budget : {kLdsPreferredFwd, kLdsMax}) {
-      if (ok) break;
-      for (int ci = 0; ci < ncand && !ok; ++ci) {
-        int* m = cand[ci];
-        double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
-        double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
-        if (diag > 1e6) continue;
-        int32_t wpa = ((int32_t)std::ceil(diag) + 5) | 1;  // odd stride spreads lanes over LDS banks
-        int nsub = m[0] * m[1] * m[2];
-        size_t lds = fp_layout(wpa, nsub, elem, pix_bytes).total;
-        if (lds <= budget) {
-          for (int a = 0; a < 3; ++a) op.msub[a] = m[a];
-          op.nsub = nsub;
-          op.wpa = wpa;
-          pl.fp_lds = lds;
-          ok = true;
-        }
-      }
-      if (ok) break;
-    }
-    if (!ok) return fail(msg, PA_ERR_UNSUPPORTED, "histogram window of one tile does not fit in LDS (h / (c dt) too large)");
-    for (int a = 0; a < 3; ++a) op.natile[a] = ceil_div(op.ntile[a], op.msub[a]);
-    op.n_atiles = op.natile[0] * op.natile[1] * op.natile[2];
-    op.n_chunks = ceil_div(g->n_sensors, kSensorsPerFwdBlock);
-    // gather of the partial rows: one work-group per (sensor, segment of kseg samples)
-    op.kseg = std::max(1, std::min<int32_t>(g->n_samples, kBlock));
-    op.nseg = g->n_samples > 0 ? ceil_div(g->n_samples, op.kseg) : 0;
-    pl.gather_lds = gather_lds();
-    const size_t rows = (size_t)op.n_atiles * (size_t)g->n_sensors * (size_t)op.wpa * elem;
-    const size_t tab = (size_t)op.n_atiles * (size_t)g->n_sensors * 4;
-    pl.part_rows_off = 0;
-    pl.klo_tab_off = align_up(rows, 256);
-    pl.fwd_scratch = align_up(pl.klo_tab_off + tab, 256);
-    if (pl.fwd_scratch > ((size_t)1 << 40)) return fail(msg, PA_ERR_UNSUPPORTED, "forward scratch above 1 TiB");
+    if (seg == 0) return fail(msg, PA_ERR_UNSUPPORTED, "forward histogram does not fit in LDS (h / (c dt) too large)");
+    op.fseg = (int32_t)std::min<int64_t>(seg, Kp);
+    op.fnseg = ceil_div(Kp, op.fseg);
+    op.fbins = bins(op.fseg);
+    pl.fp_lds = fp_layout(op.fbins, op.wp, sc_bytes, fix).total;
   }
 
-  op.out_scale = (float)(2.0 * inv_cdt);   // float path accumulates w / 2
-  op.out_scale_d = inv_cdt;                // double path accumulates w
+  op.out_scale = (float)(2.0 * inv_cdt);   // FP32 phase accumulates w / 2
+  op.out_scale_h = 2.0 * inv_cdt;
+  op.out_scale_d = inv_cdt;                // FP64 phase accumulates w
   // The adjoint runs whenever there are pixels (with no sensors or samples it
   // writes zeros, and its CGLS epilogue still has work); the forward
-  // operator only when there is something to scatter.
-  const bool empty = P == 0 || g->n_sensors == 0 || g->n_samples == 0;
+  // operator whenever there are samples to write (with no pixels its
+  // work-groups list no tile and write zeros).
   pl.bp_grid = P == 0 ? 0 : op.n_tiles;
-  pl.fp_grid = empty ? 0 : op.n_atiles * op.n_chunks;
-  pl.gather_grid = empty ? 0 : g->n_sensors * op.nseg;
+  const int64_t fwg = M == 0 ? 0 : (int64_t)g->n_sensors * op.fnseg;
+  if (fwg > std::numeric_limits<int32_t>::max()) return fail(msg, PA_ERR_UNSUPPORTED, "forward grid above 2^31-1 work-groups");
+  pl.fp_grid = (int)fwg;
   return PA_OK;
 }
 
 CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   CglsLayout L{};
   const size_t A = 256;
-  L.g_q = std::max(plan.gather_grid, 1);
+  L.g_q = std::max(plan.fp_grid, 1);
   L.g_m = blas_grid(plan.M);
   L.g_p = blas_grid(plan.P);
   L.g_bp = std::max(plan.op.n_tiles, 1);
@@ -303,7 +278,6 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
   L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.vec_p = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
-  L.fwd = off; off = align_up(off + std::max<size_t>(plan.fwd_scratch, 256), A);
   L.total = off;
   return L;
 }
@@ -327,7 +301,6 @@ LwLayout lw_layout(const Plan& plan) {
   L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
   L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.vec_v = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
-  L.fwd = off; off = align_up(off + std::max<size_t>(plan.fwd_scratch, 256), A);
   L.total = off;
   return L;
 }
@@ -360,7 +333,7 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
   // within what the planner's rules give for the batch.
   std::vector<Plan> rule(n_frames);
   size_t rule_bp = 0, rule_fp = 0;
-  const Tuning by_rule{{0, 0, 0}, 0};
+  const Tuning by_rule{0, 0, 0};
   for (int i = 0; i < n_frames; ++i) {
     std::string m;
     pa_status st = make_plan(&frames[i], dtype, &rule[i], &m, &by_rule);
@@ -377,12 +350,13 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
     std::string m;
     Plan tuned;
     if (use_tuning && make_plan(&frames[i], dtype, &tuned, &m) == PA_OK && tuned.bp_lds <= rule_bp &&
-        tuned.fp_lds <= rule_fp)
+        tuned.fp_lds <= rule_fp && tuned.op.ffix == rule[i].op.ffix)
       B.plans[i] = tuned;
     else
       B.plans[i] = rule[i];
   }
   B.tuned = use_tuning;
+  B.ffix = B.plans[0].op.ffix != 0;   // one forward kernel per launch: every frame plans the same mode
   B.ndim = frames[0].ndim;
   B.elem = B.plans[0].elem;
   // packed buffers in caller order
@@ -401,8 +375,7 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
   for (int i = 0; i < n_frames; ++i) order[i] = i;
   auto work = [&](int i) { return (double)B.plans[i].P * (double)B.plans[i].op.S; };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-  int64_t bbp = 0, bfp = 0, bga = 0, bm = 0, bpp = 0, sbp = 0, sga = 0;
-  size_t scr = 0;
+  int64_t bbp = 0, bfp = 0, bm = 0, bpp = 0, sbp = 0, sfp = 0;
   B.table.resize(n_frames);
   for (int j = 0; j < n_frames; ++j) {
     const int i = order[j];
@@ -415,30 +388,23 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
     F.yo = B.yoff[i];
     F.b_bp = (int32_t)bbp; F.n_bp = pl.bp_grid; bbp += F.n_bp;
     F.b_fp = (int32_t)bfp; F.n_fp = pl.fp_grid; bfp += F.n_fp;
-    F.b_ga = (int32_t)bga; F.n_ga = pl.M > 0 ? pl.op.S * pl.op.nseg : 0; bga += F.n_ga;
     F.b_m = (int32_t)bm; F.n_m = blas_grid(pl.M); bm += F.n_m;
     F.b_p = (int32_t)bpp; F.n_p = blas_grid(pl.P); bpp += F.n_p;
     F.s_bp = (int32_t)sbp; sbp += std::max(F.n_bp, 1);
-    F.s_ga = (int32_t)sga; sga += std::max(F.n_ga, 1);
-    F.scr = (int64_t)scr;
-    F.scr_tab = (int64_t)(scr + pl.klo_tab_off);
-    if (pl.fp_grid > 0) scr = align_up(scr + pl.fwd_scratch, 256);
+    F.s_fp = (int32_t)sfp; sfp += std::max(F.n_fp, 1);
     B.frac = B.frac || pl.op.t0f != 0.0f;
     B.bp_lds = std::max(B.bp_lds, pl.bp_lds);
     B.fp_lds = std::max(B.fp_lds, pl.fp_lds);
-    B.gather_lds = std::max(B.gather_lds, pl.gather_lds);
   }
   const int64_t lim = std::numeric_limits<int32_t>::max();
-  if (bbp > lim || bfp > lim || bga > lim || bm > lim || bpp > lim || sbp > lim || sga > lim)
+  if (bbp > lim || bfp > lim || bm > lim || bpp > lim || sbp > lim || sfp > lim)
     return fail(msg, PA_ERR_UNSUPPORTED, "batch needs more than 2^31-1 work-groups in one launch");
   B.bp_grid = (int)bbp;
   B.fp_grid = (int)bfp;
-  B.gather_grid = (int)bga;
   B.m_grid = (int)bm;
   B.p_grid = (int)bpp;
   B.bp_slots = (int)sbp;
-  B.ga_slots = (int)sga;
-  B.fwd_scratch = std::max<size_t>(scr, 256);
+  B.fp_slots = (int)sfp;
   *bp = std::move(B);
   return PA_OK;
 }
@@ -448,7 +414,6 @@ BatchLayout batch_layout(const BatchPlan& B, int32_t iters, bool cg) {
   const size_t A = 256;
   size_t off = 0;
   L.table = off; off = align_up(off + sizeof(FrameDesc) * (size_t)B.nf, A);
-  L.fwd = off; off = align_up(off + B.fwd_scratch, A);
   if (!cg) {
     L.total = off;
     return L;
@@ -458,7 +423,7 @@ BatchLayout batch_layout(const BatchPlan& B, int32_t iters, bool cg) {
   L.status = off; off = align_up(off + sizeof(int) * nf, A);
   L.gamma = off; off = align_up(off + sizeof(double) * nf * L.astride, A);
   L.alpha = off; off = align_up(off + sizeof(double) * nf * L.astride, A);
-  L.part_q = off; off = align_up(off + sizeof(double) * B.ga_slots, A);
+  L.part_q = off; off = align_up(off + sizeof(double) * B.fp_slots, A);
   L.part_r = off; off = align_up(off + sizeof(double) * B.m_grid, A);
   L.part_s = off; off = align_up(off + sizeof(double) * B.bp_slots, A);
   L.part_x = off; off = align_up(off + sizeof(double) * B.bp_slots, A);

@@ -28,10 +28,14 @@ template <> struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1; };
 template <> struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4; };
 
 constexpr int kBlock = 256;          // lanes per work-group, every kernel
-constexpr int kSensorsPerFwdBlock = 64;  // forward operator: one sensor per lane of a wave
 constexpr size_t kLdsPreferred = 64 * 1024 - 256;  // dynamic LDS that keeps several work-groups per CU
 constexpr size_t kLdsMax = 160 * 1024 - 1024;      // gfx950: 160 KiB of LDS per work-group, minus static use
-constexpr size_t kLdsPreferredFwd = 80 * 1024;      // forward pass 1: two work-groups per CU
+constexpr int kFwdList = kBlock;     // forward operator: base tiles listed per round (one per lane)
+
+// Arithmetic of a dtype: the type of every vector element (images, traces,
+// CGLS vectors) and of the per-pair delay and weight.
+PA_HD inline bool data_is_f32(pa_dtype d) { return d == PA_F32; }
+PA_HD inline bool phase_is_f32(pa_dtype d) { return d != PA_F64; }
 
 // Everything a kernel needs about the operator, by value.  Lengths are in
 // "sample units": metres multiplied by 1 / (c dt), so a distance equals its
@@ -49,20 +53,18 @@ struct OpParams {
   const double* sensors;    // device, [S][ndim], metres
   int32_t ntile[3];         // base tiles per axis
   int32_t n_tiles;          // product
-  int32_t wp;               // adjoint: LDS window stride (samples) of one sensor
+  int32_t wp;               // samples of one sensor's window over a base tile: every tap of every
+                            // pixel of the tile lies in [klo, klo + wp) (adjoint: LDS row stride)
   int32_t sc;               // adjoint: sensors staged per chunk
-  int32_t msub[3];          // forward: base tiles per forward tile, per axis
-  int32_t nsub;             // product
-  int32_t natile[3];        // forward tiles per axis
-  int32_t n_atiles;
-  int32_t n_chunks;         // forward: sensor chunks of 64
-  int32_t wpa;              // forward: LDS histogram stride of one sensor
-  int32_t kseg;             // forward gather: samples per work-group (<= 256, one per lane)
-  int32_t nseg;             // forward gather: segments per trace
+  int32_t fseg;             // forward: samples of one trace owned by a work-group
+  int32_t fnseg;            // forward: segments per trace (work-groups per sensor)
+  int32_t fbins;            // forward: histogram bins per wave, fseg + 2 wp + 2
+  int32_t ffix;             // forward, FP32 delay arithmetic: 1 = fixed-point tile rows, 0 = FP64 bins
   double near_r2;           // squared tile-centre distance (sample units) below which a
-                            // sensor takes the FP64 delay path in the FP32 kernels
-  float out_scale;          // converts accumulated kernel units to 1/metres (float path)
-  double out_scale_d;       // same, double path
+                            // sensor takes the FP64 delay path in the FP32-phase kernels
+  float out_scale;          // converts accumulated kernel units to 1/metres (FP32 phase, float data)
+  double out_scale_h;       // same in FP64 (FP32 phase accumulates w / 2)
+  double out_scale_d;       // FP64 phase (accumulates w)
 };
 
 // LDS layouts, shared by the planner (sizes) and the kernels (offsets).
@@ -82,44 +84,55 @@ PA_HD inline BpLayout bp_layout(int sc, int wp, size_t elem, size_t sc_bytes, si
   return L;
 }
 
-struct FpLayout {
-  size_t hist, pixtab, xs, klo, inv, total;
+// Forward operator, per listed base tile: its index, the offset of its
+// window in the segment's histogram, near flag and the factor that turns the
+// tile's sum of |x| into a bound on any partial sum of its taps.
+struct FpTile {
+  int32_t tile;
+  int32_t off;     // first bin of the tile's window in the FP64 histogram
+  int32_t xoff;    // index in x of the tile's first pixel
+  int32_t lim;     // pixels of the tile inside the image per axis: nx | ny << 8 | nz << 16
+  float ib;        // 1 / (2 max(dmin, r_min)), dmin = distance from the sensor to the tile's box
+  int32_t near;    // 1: FP64 delay path (FP32-phase kernels)
+  int32_t pad[2];
 };
-// Histogram bins have the element size elem: 32-bit fixed point for FP32,
-// double for FP64.  inv: per-sensor inverse fixed-point scale and the
-// per-base-tile sums of |x| that set it (FP32).
-PA_HD inline FpLayout fp_layout(int wpa, int nsub, size_t elem, size_t pix_bytes) {
+
+constexpr int kFwdGroup = 4;  // forward: list entries a wave processes together (one fixed-point scale)
+
+// Forward operator LDS: a list of up to kFwdList base tiles with their
+// per-(tile, sensor) constants (sc_bytes each), one FP64 histogram of fbins
+// bins per wave and, with fixed-point rows (fix), one int row of fbins bins
+// per wave.
+struct FpLayout {
+  size_t lst, ltab, hist, irow, total;
+};
+PA_HD inline FpLayout fp_layout(int fbins, int wp, size_t sc_bytes, bool fix) {
+  (void)wp;
   FpLayout L;
-  L.hist = 0;
-  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * elem);
-  L.xs = L.pixtab + (size_t)kBlock * pix_bytes;
-  L.klo = L.xs + align16((size_t)nsub * kBlock * elem);
-  L.inv = L.klo + align16(kSensorsPerFwdBlock * 4);
-  // inv: per-sensor inverse scale, then the per-base-tile |x| partials of four waves
-  L.total = L.inv + (kSensorsPerFwdBlock + 4 * (size_t)nsub) * sizeof(double);
+  L.lst = 0;
+  L.ltab = align16((size_t)kFwdList * sc_bytes);
+  L.hist = L.ltab + align16((size_t)kFwdList * sizeof(FpTile));
+  L.irow = L.hist + 4 * (size_t)fbins * sizeof(double);
+  L.total = L.irow + (fix ? 4 * align16((size_t)fbins * 4) : 0);
   return L;
 }
-
-// forward gather: no dynamic LDS (each wave keeps its tile selection in registers)
-PA_HD inline size_t gather_lds() { return 0; }
 
 struct Plan {
   OpParams op;
   int ndim;
   pa_dtype dtype;
-  size_t elem;              // sizeof(T)
+  size_t elem;              // bytes of one vector element
   int64_t P, M;             // pixels, samples (S*K)
-  size_t bp_lds, fp_lds, gather_lds;  // dynamic LDS bytes
-  int bp_grid, fp_grid, gather_grid;
-  size_t fwd_scratch;       // bytes of forward-operator scratch (partial rows + window table)
-  size_t part_rows_off, klo_tab_off;  // offsets inside that scratch
+  size_t bp_lds, fp_lds;    // dynamic LDS bytes
+  int bp_grid, fp_grid;     // adjoint: one work-group per base tile; forward: one per (sensor, segment)
 };
 
 // Tiling choices an autotuning run can fix for a geometry shape.  Zero
 // fields leave the planner's own choice.
 struct Tuning {
-  int32_t fwd_tile[3];   // forward operator: base tiles per forward tile, per axis
+  int32_t fwd_seg;       // forward operator: samples of a trace per work-group
   int32_t adj_lds;       // adjoint: LDS budget per work-group (bytes) that sets the sensor chunk
+  int32_t fwd_mode;      // forward, FP32 delay arithmetic: 1 = fixed-point tile rows, 2 = FP64 bins
 };
 
 // Fills *plan from g.  Returns PA_OK or an error with *msg set.  Never touches
@@ -133,8 +146,11 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
 void tune_store(const pa_geometry* g, pa_dtype dtype, const Tuning& t);
 bool tune_lookup(const pa_geometry* g, pa_dtype dtype, Tuning* t);
 void tune_clear();
-// Candidate tilings the autotuner times for a geometry of this ndim.
-int fwd_tile_candidates(int ndim, int (*out)[3], int max);
+// Changes whenever the table does: anything cached from a plan (captured
+// graphs) is stale once the epoch it was made under has passed.
+uint64_t tune_epoch();
+// Candidate tilings the autotuner times.
+int fwd_seg_candidates(int32_t* out, int max);
 int adj_lds_candidates(size_t* out, int max);
 
 // One frame of a batch as the batched kernels see it (device table, sorted
@@ -145,15 +161,12 @@ int adj_lds_candidates(size_t* out, int max);
 struct FrameDesc {
   OpParams op;
   int64_t xo, yo;      // element offsets of the frame's image / traces in the packed buffers
-  int64_t scr;         // byte offset of the frame's forward partial rows in the scratch area
-  int64_t scr_tab;     // byte offset of the frame's window-start table in the scratch area
   int32_t b_bp, n_bp;  // adjoint blocks (n_bp = 0 without pixels)
-  int32_t b_fp, n_fp;  // forward pass-1 blocks (0 when the frame is empty)
-  int32_t b_ga, n_ga;  // forward gather blocks (S * nseg whenever S * K > 0)
+  int32_t b_fp, n_fp;  // forward blocks (S * fnseg whenever S * K > 0, pixels or not)
   int32_t b_m, n_m;    // BLAS blocks over the frame's S*K samples (>= 1)
   int32_t b_p, n_p;    // BLAS blocks over the frame's pixels (>= 1)
   int32_t s_bp;        // first slot of the frame's adjoint partials (max(n_bp, 1) slots)
-  int32_t s_ga;        // first slot of the frame's gather partials (max(n_ga, 1) slots)
+  int32_t s_fp;        // first slot of the frame's forward partials (max(n_fp, 1) slots)
   int32_t frame;       // position in the caller's frame order
   int32_t pad;
 };
@@ -166,13 +179,13 @@ struct BatchPlan {
   pa_dtype dtype = PA_F32;
   size_t elem = 4;
   bool frac = false;
+  bool ffix = false;              // forward accumulation mode shared by every frame
   std::vector<Plan> plans;        // caller order
   std::vector<FrameDesc> table;   // work order (largest first)
   std::vector<int64_t> xoff, yoff;  // caller order, nf + 1 prefix offsets (elements)
-  int bp_grid = 0, fp_grid = 0, gather_grid = 0, m_grid = 0, p_grid = 0;
-  int bp_slots = 0, ga_slots = 0;
-  size_t bp_lds = 0, fp_lds = 0, gather_lds = 0;
-  size_t fwd_scratch = 0;
+  int bp_grid = 0, fp_grid = 0, m_grid = 0, p_grid = 0;
+  int bp_slots = 0, fp_slots = 0;
+  size_t bp_lds = 0, fp_lds = 0;
   int64_t P_total = 0, M_total = 0;
   bool tuned = false;             // planned with the recorded per-frame tunings
 };
@@ -182,10 +195,10 @@ struct BatchPlan {
 pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype dtype, BatchPlan* bp,
                           std::string* msg, bool use_tuning = false);
 
-// Workspace of batched calls: the device frame table, the forward scratch
-// and (cg) the per-frame CGLS state for `iters` iterations, partials and vectors.
+// Workspace of batched calls: the device frame table and (cg) the per-frame
+// CGLS state for `iters` iterations, partials and vectors.
 struct BatchLayout {
-  size_t table, status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, fwd, total;
+  size_t table, status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, total;
   int astride;   // doubles per frame in gamma and alpha (iters + 2)
 };
 BatchLayout batch_layout(const BatchPlan& bp, int32_t iters, bool cg);
@@ -196,14 +209,14 @@ int blas_grid(int64_t n);
 
 // CGLS workspace layout.
 struct CglsLayout {
-  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, fwd, total;
-  int g_q, g_m, g_p, g_bp;  // partial counts: forward gather, over S*K, over pixels, adjoint tiles
+  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, total;
+  int g_q, g_m, g_p, g_bp;  // partial counts: forward work-groups, over S*K, over pixels, adjoint tiles
 };
 CglsLayout cgls_layout(const Plan& plan, int32_t iters);
 
 // Landweber workspace layout.
 struct LwLayout {
-  size_t status, alpha0, sigma2, omega, part_r, part_s, part_x, part_n, vec_r, vec_q, vec_s, vec_v, fwd, total;
+  size_t status, alpha0, sigma2, omega, part_r, part_s, part_x, part_n, vec_r, vec_q, vec_s, vec_v, total;
   int g_m, g_p, g_bp;
 };
 LwLayout lw_layout(const Plan& plan);

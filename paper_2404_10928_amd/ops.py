@@ -69,12 +69,28 @@ def as_device_geometry(g, device=None) -> DeviceGeometry:
     return g if isinstance(g, DeviceGeometry) else DeviceGeometry(g, device)
 
 
-def _code(t: torch.Tensor) -> int:
-    if t.dtype == torch.float32:
+PRECISIONS = ("f32", "f64", "mixed")
+
+
+def dtype_code(dtype: torch.dtype, precision: str | None = None) -> int:
+    """The C ABI's dtype for tensors of `dtype`: float32 -> PA_F32, float64 ->
+    PA_F64; precision="mixed" (float64 tensors) -> PA_MIXED, FP32 delay
+    arithmetic with every vector and sum in FP64."""
+    if precision is not None and precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {PRECISIONS}")
+    if dtype == torch.float32:
+        if precision not in (None, "f32"):
+            raise TypeError(f"precision {precision!r} needs float64 tensors")
         return _lib.PA_F32
-    if t.dtype == torch.float64:
-        return _lib.PA_F64
-    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+    if dtype == torch.float64:
+        if precision == "f32":
+            raise TypeError("precision 'f32' needs float32 tensors")
+        return _lib.PA_MIXED if precision == "mixed" else _lib.PA_F64
+    raise TypeError(f"unsupported dtype {dtype}; use float32 or float64")
+
+
+def _code(t: torch.Tensor, precision: str | None = None) -> int:
+    return dtype_code(t.dtype, precision)
 
 
 def _stream(dev) -> int:
@@ -103,18 +119,18 @@ def _frames(t: torch.Tensor, per: int):
 _BATCHES: dict = {}
 
 
-def _frames_batch(g: "DeviceGeometry", n: int, dtype: torch.dtype) -> "Batch":
+def _frames_batch(g: "DeviceGeometry", n: int, dtype: torch.dtype, precision: str | None = None) -> "Batch":
     """A cached batch of n copies of one geometry (frames of a leading batch dimension)."""
-    key = (id(g), n, dtype)
+    key = (id(g), n, dtype, precision)
     b = _BATCHES.get(key)
     if b is None or b.geoms[0] is not g:
         if len(_BATCHES) > 32:
             _BATCHES.clear()
-        b = _BATCHES[key] = Batch([g] * n, dtype, g.device)
+        b = _BATCHES[key] = Batch([g] * n, dtype, g.device, precision=precision)
     return b
 
 
-def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Tensor:
+def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None, precision: str | None = None) -> torch.Tensor:
     """y := A x.  Leading batch dimensions of x are frames, applied in one
     batched launch per pass (the single-frame result for every frame)."""
     g = as_device_geometry(geom, x.device)
@@ -129,17 +145,17 @@ def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Ten
     if M and len(xs) != len(ys):
         raise ValueError("x and y hold different numbers of frames")
     if len(xs) > 1 and P and M:
-        _frames_batch(g, len(xs), x.dtype).forward(x.reshape(-1), out.reshape(-1))
+        _frames_batch(g, len(xs), x.dtype, precision).forward(x.reshape(-1), out.reshape(-1))
         return out
     lib = _lib.load()
     cg = g.c_struct()
     for xb, yb in zip(xs, ys):
-        _lib.check(lib.pa_forward(ctypes.byref(cg), _code(x), xb.data_ptr() or None, yb.data_ptr() or None,
-                                  _stream(x.device)))
+        _lib.check(lib.pa_forward(ctypes.byref(cg), _code(x, precision), xb.data_ptr() or None,
+                                  yb.data_ptr() or None, _stream(x.device)))
     return out
 
 
-def adjoint(y: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Tensor:
+def adjoint(y: torch.Tensor, geom, out: torch.Tensor | None = None, precision: str | None = None) -> torch.Tensor:
     """x := A^T y.  Leading batch dimensions of y are frames, applied in one
     batched launch (the single-frame result for every frame)."""
     g = as_device_geometry(geom, y.device)
@@ -154,13 +170,13 @@ def adjoint(y: torch.Tensor, geom, out: torch.Tensor | None = None) -> torch.Ten
     if P and len(xs) != len(ys):
         raise ValueError("x and y hold different numbers of frames")
     if len(ys) > 1 and P and M:
-        _frames_batch(g, len(ys), y.dtype).adjoint(y.reshape(-1), out.reshape(-1))
+        _frames_batch(g, len(ys), y.dtype, precision).adjoint(y.reshape(-1), out.reshape(-1))
         return out
     lib = _lib.load()
     cg = g.c_struct()
     for yb, xb in zip(ys, xs):
-        _lib.check(lib.pa_adjoint(ctypes.byref(cg), _code(y), yb.data_ptr() or None, xb.data_ptr() or None,
-                                  _stream(y.device)))
+        _lib.check(lib.pa_adjoint(ctypes.byref(cg), _code(y, precision), yb.data_ptr() or None,
+                                  xb.data_ptr() or None, _stream(y.device)))
     return out
 
 
@@ -172,10 +188,10 @@ class Operator:
     forward()/adjoint().
     """
 
-    def __init__(self, geom, dtype: torch.dtype = torch.float32, device=None):
+    def __init__(self, geom, dtype: torch.dtype = torch.float32, device=None, precision: str | None = None):
         self.geom = as_device_geometry(geom, device)
         self.dtype = dtype
-        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._code = dtype_code(dtype, precision)
         self._cg = self.geom.c_struct()
         self._ref = ctypes.byref(self._cg)
         self._lib = _lib.load()
@@ -192,10 +208,10 @@ class Operator:
         return x
 
 
-def cgls_workspace_bytes(geom, dtype: torch.dtype, iters: int) -> int:
+def cgls_workspace_bytes(geom, dtype: torch.dtype, iters: int, precision: str | None = None) -> int:
     g = as_device_geometry(geom)
     lib = _lib.load()
-    code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+    code = dtype_code(dtype, precision)
     n = lib.pa_cgls_workspace_bytes(ctypes.byref(g.c_struct()), code, int(iters))
     if n == 0:
         raise _lib.PaError(_lib.PA_ERR_INVALID_ARGUMENT, _lib.last_error())
@@ -205,14 +221,17 @@ def cgls_workspace_bytes(geom, dtype: torch.dtype, iters: int) -> int:
 class CglsSolver:
     """Owns the device workspace and history of repeated solves on one geometry."""
 
-    def __init__(self, geom, dtype: torch.dtype, iters: int, lam: float, graph: bool = True, device=None):
+    def __init__(self, geom, dtype: torch.dtype, iters: int, lam: float, graph: bool = True, device=None,
+                 precision: str | None = None):
         self.geom = as_device_geometry(geom, device)
         self.dtype = dtype
+        self.precision = precision
+        self._code = dtype_code(dtype, precision)
         self.iters = int(iters)
         self.lam = float(lam)
         self.graph = graph
         dev = self.geom.device
-        nbytes = cgls_workspace_bytes(self.geom, dtype, self.iters)
+        nbytes = cgls_workspace_bytes(self.geom, dtype, self.iters, precision)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.history = torch.zeros((self.iters + 1, 3), dtype=torch.float64, device=dev)
         self._cg = self.geom.c_struct()
@@ -228,7 +247,7 @@ class CglsSolver:
             raise TypeError("y and x must match the solver dtype")
         flags = (_lib.PA_X0_ZERO if x0_zero else 0) | (_lib.PA_USE_GRAPH if self.graph else 0)
         lib = _lib.load()
-        _lib.check(lib.pa_cgls_solve(ctypes.byref(self._cg), _code(y), y.data_ptr() or None, x.data_ptr() or None,
+        _lib.check(lib.pa_cgls_solve(ctypes.byref(self._cg), self._code, y.data_ptr() or None, x.data_ptr() or None,
                                      self.iters, self.lam, flags, self.workspace.data_ptr(),
                                      self.workspace.numel(), self.history.data_ptr(), _stream(y.device)))
         return x
@@ -242,9 +261,11 @@ class CglsSolver:
         return int(out.value)
 
 
-def cgls(y: torch.Tensor, geom, iters: int, lam: float, x0: torch.Tensor | None = None, graph: bool = True):
-    """CGLS on ||A x - y||^2 + lam ||x||^2.  Returns (x, history[iters+1][3], stop_iteration)."""
-    solver = CglsSolver(geom, y.dtype, iters, lam, graph=graph, device=y.device)
+def cgls(y: torch.Tensor, geom, iters: int, lam: float, x0: torch.Tensor | None = None, graph: bool = True,
+         precision: str | None = None):
+    """CGLS on ||A x - y||^2 + lam ||x||^2.  Returns (x, history[iters+1][3], stop_iteration).
+    precision="mixed" (float64 y): FP64 vectors and sums around the FP32-arithmetic operator."""
+    solver = CglsSolver(geom, y.dtype, iters, lam, graph=graph, device=y.device, precision=precision)
     if x0 is None:
         x = solver.solve(y.contiguous())
     else:
@@ -264,13 +285,13 @@ class Batch:
     per-frame tensors.
     """
 
-    def __init__(self, geoms, dtype: torch.dtype = torch.float32, device=None):
+    def __init__(self, geoms, dtype: torch.dtype = torch.float32, device=None, precision: str | None = None):
         self.geoms = [as_device_geometry(g, device) for g in geoms]
         if not self.geoms:
             raise ValueError("a batch needs at least one frame")
         self.device = self.geoms[0].device
         self.dtype = dtype
-        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._code = dtype_code(dtype, precision)
         self._structs = (_lib.PaGeometry * len(self.geoms))(*[g.c_struct() for g in self.geoms])
         self._lib = _lib.load()
         h = ctypes.c_void_p()
@@ -393,7 +414,7 @@ class Batch:
         return [int(v) for v in out]
 
 
-def autotune(geom, dtype: torch.dtype = torch.float32, device=None) -> dict:
+def autotune(geom, dtype: torch.dtype = torch.float32, device=None, precision: str | None = None) -> dict:
     """Times the candidate tilings of A and A^T on this geometry and records the
     fastest for every later plan of the same shape (process-wide).  Returns the
     choice and its measured times."""
@@ -402,9 +423,10 @@ def autotune(geom, dtype: torch.dtype = torch.float32, device=None) -> dict:
     y = torch.zeros(g.data_shape, dtype=dtype, device=g.device)
     t = _lib.PaTuning()
     lib = _lib.load()
-    _lib.check(lib.pa_autotune(ctypes.byref(g.c_struct()), _code(x), x.data_ptr() or None, y.data_ptr() or None,
+    _lib.check(lib.pa_autotune(ctypes.byref(g.c_struct()), _code(x, precision), x.data_ptr() or None,
+                               y.data_ptr() or None,
                                _stream(g.device), ctypes.byref(t)))
-    return {"fwd_tile": tuple(int(v) for v in t.fwd_tile), "adj_lds_bytes": int(t.adj_lds_bytes),
+    return {"fwd_seg": int(t.fwd_seg), "fwd_mode": int(t.fwd_mode), "adj_lds_bytes": int(t.adj_lds_bytes),
             "fwd_us": float(t.fwd_us), "adj_us": float(t.adj_us)}
 
 
@@ -420,12 +442,12 @@ class LandweberSolver:
     power_iters power-iteration steps (omega = 1 / (sigma2 + lam))."""
 
     def __init__(self, geom, dtype: torch.dtype, iters: int, lam: float, omega: float = 0.0, power_iters: int = 30,
-                 graph: bool = True, device=None):
+                 graph: bool = True, device=None, precision: str | None = None):
         self.geom = as_device_geometry(geom, device)
         self.dtype = dtype
         self.iters, self.lam, self.omega, self.power_iters = int(iters), float(lam), float(omega), int(power_iters)
         self.graph = graph
-        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._code = dtype_code(dtype, precision)
         self._cg = self.geom.c_struct()
         lib = _lib.load()
         n = lib.pa_landweber_workspace_bytes(ctypes.byref(self._cg), self._code)
@@ -483,13 +505,13 @@ class FistaSolver:
 
     def __init__(self, geom, dtype: torch.dtype, iters: int, lam: float, alpha: float, beta: float,
                  eps: float = 1e-2, omega: float = 0.0, power_iters: int = 30, nonneg: bool = False,
-                 graph: bool = True, device=None):
+                 graph: bool = True, device=None, precision: str | None = None):
         self.geom = as_device_geometry(geom, device)
         self.dtype = dtype
         self.iters, self.lam, self.alpha, self.beta = int(iters), float(lam), float(alpha), float(beta)
         self.eps, self.omega, self.power_iters = float(eps), float(omega), int(power_iters)
         self.nonneg, self.graph = bool(nonneg), graph
-        self._code = _lib.PA_F32 if dtype == torch.float32 else _lib.PA_F64
+        self._code = dtype_code(dtype, precision)
         self._cg = self.geom.c_struct()
         lib = _lib.load()
         n = lib.pa_fista_workspace_bytes(ctypes.byref(self._cg), self._code)

@@ -48,7 +48,7 @@ def test_every_declared_symbol_is_exported(lib):
     assert {"pa_forward", "pa_adjoint", "pa_cgls_solve", "pa_cgls_workspace_bytes"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.pa_abi_version() == 1
+    assert lib.pa_abi_version() == 2
 
 
 def good():

@@ -1,11 +1,9 @@
 """Batched frames of uneven size (one launch per step for every frame) against
 the single-frame calls and the FP64 oracle.
 
-The adjoint and the solver steps run the single-frame device code on each
-frame's plan with every partial sum in the same order, so a batched adjoint
-equals the single-frame adjoint bit for bit.  The forward operator adds its
-FP64 histogram terms in hardware order, so batched and single-frame forward
-results agree to the rounding of those sums.
+Both operators and the solver steps run the single-frame device code on each
+frame's plan with every partial sum in the same order, so a batched result
+equals the single-frame result bit for bit.
 """
 import numpy as np
 import pytest
@@ -71,17 +69,14 @@ def test_batched_operators_match_single_frames(pa, dt):
         xs_single = single(pa, pa.adjoint, g, ys[i][0], dt)
         # adjoint: bit for bit
         assert np.array_equal(xb[i], xs_single), f"frame {i}: batched adjoint differs from the single-frame one"
-        # forward: to the rounding of the FP64 histogram sums
+        # forward: bit for bit as well (every sum in a fixed order)
         assert yb[i].shape == ys_single.shape and xb[i].shape == xs_single.shape
-        if ys_single.size:
-            scale = max(np.abs(ys_single).max(), 1e-300)
-            assert np.abs(yb[i] - ys_single).max() <= (1e-6 if dt == np.float32 else 1e-13) * scale, f"frame {i}"
+        assert np.array_equal(yb[i], ys_single), f"frame {i}: batched forward differs from the single-frame one"
         if g.n_pixels and g.n_sensors and g.n_samples:
             assert rel_l2(yb[i], oracle.forward(g, xs[i][1])) <= gate
             assert rel_l2(xb[i], oracle.adjoint(g, ys[i][1])) <= gate
         else:
             assert not np.any(yb[i]) and not np.any(xb[i])
-        print(f"{np.dtype(dt).name} frame {i}: forward bitwise equal {np.array_equal(yb[i], ys_single)}")
 
 
 def test_batched_3d_operators(pa):
@@ -173,7 +168,7 @@ def test_autotune_records_a_tiling_and_keeps_results(pa):
     before_a = single(pa, pa.adjoint, g, y, np.float32)
     t = pa.autotune(g, torch.float32)
     print("tuning:", t)
-    assert all(v >= 1 for v in t["fwd_tile"]) and t["adj_lds_bytes"] > 0 and t["fwd_us"] > 0 and t["adj_us"] > 0
+    assert t["fwd_seg"] >= 1 and t["adj_lds_bytes"] > 0 and t["fwd_us"] > 0 and t["adj_us"] > 0
     after_f = single(pa, pa.forward, g, x, np.float32)
     after_a = single(pa, pa.adjoint, g, y, np.float32)
     # another tiling changes only the order of sums

@@ -115,9 +115,16 @@ def test_coarse_and_fine_pitch(pa):
     check_pair(pa, g2, 9, label="coarse dt")
 
 
+def test_coarse_pitch_matches_oracle(pa):
+    # h / (c dt) ~ 60 samples per pixel: a base tile's window spans ~1280
+    # samples, still within LDS for both operators
+    g = ring_geom(n=(30, 30), S=40, K=2700)
+    check_pair(pa, g, 15, label="60 samples per pixel")
+
+
 def test_pitch_beyond_lds_window_is_unsupported(pa):
     import paper_2404_10928_amd._lib as L
-    g = ring_geom(n=(30, 30), S=40, K=2700)   # h / (c dt) ~ 60 samples per pixel
+    g = ring_geom(n=(30, 30), S=40, K=9000)   # h / (c dt) ~ 200 samples per pixel
     with pytest.raises(L.PaError) as e:
         pa.forward(torch.ones(g.image_shape, dtype=torch.float32, device="cuda"), g)
     assert e.value.status == L.PA_ERR_UNSUPPORTED

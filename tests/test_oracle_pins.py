@@ -247,6 +247,59 @@ def test_cgls_iterates_minimise_over_krylov_spaces():
         prevF = F
 
 
+def test_cgls_reorder_floor():
+    """How far a correct CGLS may sit from the oracle's when it sums in another
+    order.  On a 64x48 image with a 96-sensor ring and 320 samples (the GPU
+    graph-versus-eager problem), CGLS written with numpy on the dense matrix
+    built from the oracle's own operator columns follows the oracle to 1e-10
+    for 8 iterations, then departs at ~20x per two iterations (3e-8 at 12):
+    the rounding of CG's inner products, not the operator, sets that floor.
+    Both solves are the textbook recursion, so their agreement at k <= 8 also
+    pins the oracle's CGLS on a problem far larger than the tiny ones above."""
+    import math as _m
+    from synth import Geometry as _G
+    nx, ny, S, K, h = 64, 48, 96, 320, 1e-4
+    hd = _m.hypot(nx - 1, ny - 1) * h / 2
+    rad = 1.2 * hd
+    g = _G(2, nx, ny, 1, h, (0.0, 0.0, 0.0), ring_sensors(S, rad), K, (rad + hd) / (1500.0 * (K - 4)))
+    rng = np.random.default_rng(21)
+    y = oracle.forward(g, rng.uniform(size=g.image_shape)) + 0.01 * rng.normal(size=g.data_shape)
+    P = g.n_pixels
+    A = np.empty((g.n_sensors * g.n_samples, P))
+    e = np.zeros(P)
+    for p in range(P):
+        e[p] = 1.0
+        A[:, p] = oracle.forward(g, e.reshape(g.image_shape)).reshape(-1)
+        e[p] = 0.0
+
+    def cgls(n, lam=1e-3):
+        x = np.zeros(P)
+        r = y.reshape(-1).copy()
+        s = A.T @ r
+        p_ = s.copy()
+        gam = s @ s
+        for _ in range(n):
+            q = A @ p_
+            a = gam / (q @ q + lam * (p_ @ p_))
+            x += a * p_
+            r -= a * q
+            s = A.T @ r - lam * x
+            g2 = s @ s
+            p_ = s + (g2 / gam) * p_
+            gam = g2
+        return x
+
+    def rel(n):
+        xo, _, _ = oracle.cgls(g, y, n, 1e-3)
+        xd = cgls(n)
+        return np.linalg.norm(xd - xo.reshape(-1)) / np.linalg.norm(xo)
+
+    e8, e12 = rel(8), rel(12)
+    print(f"dense CGLS vs oracle: {e8:.2e} at k = 8, {e12:.2e} at k = 12")
+    assert e8 <= 1e-9
+    assert 1e-9 <= e12 <= 1e-7
+
+
 def test_cgls_warm_start_and_breakdown():
     g, y = tiny_problem(3)
     # y = 0 with x0 = 0: gamma_0 = 0, stops at iteration 0 with x = 0
