@@ -92,6 +92,18 @@ pa_status pa_validate_geometry(const pa_geometry* g, pa_dtype dtype);
  * same type.  The time-domain operator of Eq. 6 as stated above. */
 pa_status pa_forward(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* hip_stream);
 
+/* y := A x as pa_forward, with a caller-owned device workspace of
+ * pa_forward_workspace_bytes() bytes (256-byte aligned; may be NULL when that
+ * size is 0).  With PA_F32, once pa_autotune has chosen the partial-row method
+ * for this shape, the operator runs in two passes through the workspace: pass
+ * 1 scatters each forward tile's taps for 64 sensors into LDS rows, written to
+ * the workspace; pass 2 adds each sensor's rows up.  Both methods form every
+ * sum in a fixed order; they round differently (each within the same bound
+ * of the exact operator).  Otherwise it is pa_forward. */
+size_t pa_forward_workspace_bytes(const pa_geometry* g, pa_dtype dtype);
+pa_status pa_forward_ws(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* workspace,
+                        size_t workspace_bytes, void* hip_stream);
+
 /* x := A^T y, delay-and-interpolate back-projection: the exact adjoint of
  * pa_forward (the K^T products of Table 4). */
 pa_status pa_adjoint(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, void* hip_stream);
@@ -307,18 +319,32 @@ pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int
  * included, plans with the recorded tiling.  Tilings change only the order
  * of floating-point sums, not the operator.  x, y: device buffers of the
  * geometry's image and trace sizes, used as scratch (their contents are
- * overwritten).  Synchronises the stream.  May allocate the forward
- * operator's internal scratch (as pa_forward does). */
+ * overwritten).  Synchronises the stream.  Allocates no device memory:
+ * the partial-row forward is timed in the caller's workspace. */
 typedef struct {
-  int32_t fwd_seg;         /* samples of one trace per forward work-group (0: no forward work) */
+  int32_t fwd_seg;         /* samples of one trace per sensor-major forward work-group (0: no forward work) */
   int32_t adj_lds_bytes;   /* adjoint LDS budget that sets its sensor chunk (0: no adjoint work) */
-  int32_t fwd_mode;        /* forward accumulation with FP32 delay arithmetic: 1 = fixed-point tile rows,
-                              2 = FP64 bins (0 under PA_F64, which always uses FP64 bins) */
-  int32_t pad;
+  int32_t fwd_mode;        /* forward method: 1 = sensor-major, fixed-point tile rows; 2 = sensor-major,
+                              FP64 bins; 3 = partial rows (PA_F32 with a workspace; otherwise mode 1);
+                              0 under PA_F64, which always uses FP64 bins */
+  int32_t fwd_tile[3];     /* mode 3: base tiles per forward tile, per axis */
   double fwd_us, adj_us;   /* measured time per apply of the chosen tilings */
 } pa_tuning;
 
-pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, void* hip_stream, pa_tuning* out);
+/* Device workspace that lets pa_autotune time the partial-row forward
+ * method (PA_F32); 0 when there is nothing to time with it.  Without it (a
+ * NULL workspace) pa_autotune times the sensor-major method only. */
+size_t pa_autotune_workspace_bytes(const pa_geometry* g, pa_dtype dtype);
+pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, void* workspace, size_t workspace_bytes,
+                      void* hip_stream, pa_tuning* out);
+
+/* Records t as the tuning of g's shape, as pa_autotune would (for instance
+ * one saved from an earlier process).  fwd_us / adj_us are ignored; zero
+ * fields keep the planner's rule.  Host only.  PA_ERR_INVALID_ARGUMENT for
+ * out-of-range fields, PA_ERR_UNSUPPORTED when the planner cannot take a
+ * requested choice (a segment or forward tile whose LDS does not fit, fwd_mode
+ * 3 outside PA_F32); nothing is recorded then. */
+pa_status pa_tuning_set(const pa_geometry* g, pa_dtype dtype, const pa_tuning* t);
 
 /* Forgets every recorded tiling (later plans use the planner's rules). */
 pa_status pa_tuning_clear(void);

@@ -30,10 +30,11 @@ PA_X0_ZERO = 1
 PA_USE_GRAPH = 2
 PA_NONNEG = 4
 
-EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspace_bytes", "pa_cgls_solve",
+EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_forward_workspace_bytes", "pa_forward_ws", "pa_adjoint",
+           "pa_autotune_workspace_bytes", "pa_cgls_workspace_bytes", "pa_cgls_solve",
            "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version", "pa_batch_create", "pa_batch_destroy",
            "pa_batch_offsets", "pa_batch_workspace_bytes", "pa_batch_cgls_workspace_bytes", "pa_batch_forward",
-           "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations", "pa_autotune", "pa_tuning_clear",
+           "pa_batch_adjoint", "pa_batch_cgls_solve", "pa_batch_stop_iterations", "pa_autotune", "pa_tuning_set", "pa_tuning_clear",
            "pa_landweber_workspace_bytes", "pa_landweber_solve", "pa_landweber_step",
            "pa_batch_autotune_workspace_bytes", "pa_batch_autotune", "pa_fista_workspace_bytes", "pa_fista_solve",
            "pa_fista_step", "pa_dense_matrix_bytes", "pa_dense_build", "pa_dense_forward",
@@ -43,7 +44,7 @@ EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_adjoint", "pa_cgls_workspac
 
 class PaTuning(ctypes.Structure):
     _fields_ = [("fwd_seg", ctypes.c_int32), ("adj_lds_bytes", ctypes.c_int32), ("fwd_mode", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("fwd_us", ctypes.c_double), ("adj_us", ctypes.c_double)]
+                ("fwd_tile", ctypes.c_int32 * 3), ("fwd_us", ctypes.c_double), ("adj_us", ctypes.c_double)]
 
 
 class PaGeometry(ctypes.Structure):
@@ -74,6 +75,10 @@ def load(path: str = LIB_PATH):
     lib.pa_validate_geometry.restype = ctypes.c_int
     lib.pa_forward.argtypes = [gp, ctypes.c_int, vp, vp, vp]
     lib.pa_forward.restype = ctypes.c_int
+    lib.pa_forward_workspace_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_forward_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_forward_ws.argtypes = [gp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.pa_forward_ws.restype = ctypes.c_int
     lib.pa_adjoint.argtypes = [gp, ctypes.c_int, vp, vp, vp]
     lib.pa_adjoint.restype = ctypes.c_int
     lib.pa_cgls_workspace_bytes.argtypes = [gp, ctypes.c_int, ctypes.c_int32]
@@ -107,8 +112,12 @@ def load(path: str = LIB_PATH):
     lib.pa_batch_cgls_solve.restype = ctypes.c_int
     lib.pa_batch_stop_iterations.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.pa_batch_stop_iterations.restype = ctypes.c_int
-    lib.pa_autotune.argtypes = [gp, ctypes.c_int, vp, vp, vp, ctypes.POINTER(PaTuning)]
+    lib.pa_autotune_workspace_bytes.argtypes = [gp, ctypes.c_int]
+    lib.pa_autotune_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_autotune.argtypes = [gp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(PaTuning)]
     lib.pa_autotune.restype = ctypes.c_int
+    lib.pa_tuning_set.argtypes = [gp, ctypes.c_int, ctypes.POINTER(PaTuning)]
+    lib.pa_tuning_set.restype = ctypes.c_int
     lib.pa_tuning_clear.argtypes = []
     lib.pa_tuning_clear.restype = ctypes.c_int
     lib.pa_landweber_workspace_bytes.argtypes = [gp, ctypes.c_int]

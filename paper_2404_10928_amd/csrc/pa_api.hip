@@ -92,6 +92,7 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
   void* q = ws + L.vec_q;
   void* s = ws + L.vec_s;
   void* p = ws + L.vec_p;
+  void* fwd = ws + L.fwd;   // partial rows of the forward operator (when its plan uses them)
   hipError_t e;
   const int gbp = std::max(pl.bp_grid, 1);
 
@@ -100,7 +101,7 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
     if ((e = pa::launch_fill(dt, S.x, pl.P, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, nullptr, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
   } else {
-    if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, S.x, q, nullptr, fwd, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha, st)) != hipSuccess) return e;
   }
   pa::CgArgs cg{S.x, p, alpha, S.lambda, part_s, part_x};
@@ -120,7 +121,7 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
     return e;
   for (int k = 0; k < S.iters; ++k) {
     // q = A p with the FP64 partials of ||q||^2
-    if ((e = pa::launch_forward(pl, p, q, part_q, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, p, q, part_q, fwd, st)) != hipSuccess) return e;
     if ((e = pa::launch_upd_r(dt, r, q, pl.M, part_q, L.g_q, part_p, L.g_p, S.lambda, gamma + k, alpha + k + 1, status,
                               k, part_r, st)) != hipSuccess)
       return e;
@@ -165,13 +166,14 @@ hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
   void* q = ws + L.vec_q;
   void* s = ws + L.vec_s;
   void* v = ws + L.vec_v;
+  void* fwd = ws + L.fwd;
   hipError_t e;
   // step size
   if ((e = pa::launch_fill(PA_F64, sigma2, 1, st)) != hipSuccess) return e;
   if (!(S.omega > 0.0) && pl.P > 0) {
     if ((e = pa::launch_fill_value(dt, v, pl.P, 1.0 / std::sqrt((double)pl.P), st)) != hipSuccess) return e;
     for (int it = 0; it < S.power_iters; ++it) {
-      if ((e = pa::launch_forward(pl, v, q, nullptr, st)) != hipSuccess) return e;
+      if ((e = pa::launch_forward(pl, v, q, nullptr, fwd, st)) != hipSuccess) return e;
       if (pl.bp_grid > 0 && (e = pa::launch_adjoint(pl, q, s, nullptr, st)) != hipSuccess) return e;
       if ((e = pa::launch_norm2(dt, s, pl.P, part_n, st)) != hipSuccess) return e;
       if ((e = pa::launch_pw_scale(dt, v, s, pl.P, part_n, sigma2, st)) != hipSuccess) return e;
@@ -184,7 +186,7 @@ hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
   // s = A^T r - lambda x with x unchanged (the epilogue's step is the zero that init_r writes)
   pa::CgArgs cg{S.x, S.x, alpha0, S.lambda, part_s, part_x};
   for (int k = 0; k < S.iters; ++k) {
-    if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, S.x, q, nullptr, fwd, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
     if (pl.bp_grid == 0) {
       if ((e = pa::launch_fill(PA_F64, part_s, gbp, st)) != hipSuccess) return e;
@@ -197,7 +199,7 @@ hipError_t enqueue_landweber(const LwSolve& S, hipStream_t st) {
       return e;
   }
   // F at the final iterate
-  if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
+  if ((e = pa::launch_forward(pl, S.x, q, nullptr, fwd, st)) != hipSuccess) return e;
   if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
   if ((e = pa::launch_norm2(dt, S.x, pl.P, part_n, st)) != hipSuccess) return e;
   return pa::launch_lw_final(part_r, L.g_m, part_n, L.g_p, S.lambda, S.hist, S.iters, st);
@@ -240,6 +242,7 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
   void* s = ws + L.vec_s;
   void* v = ws + L.vec_v;
   void* zb[2] = {ws + S.F.vec_z0, ws + S.F.vec_z1};
+  void* fwd = ws + L.fwd;
   const int nonneg = (S.flags & PA_NONNEG) ? 1 : 0;
   hipError_t e;
   // step: 1 / (sigma2 + lambda + 4 beta / eps), the inverse Lipschitz constant
@@ -248,7 +251,7 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
   if (!(S.omega > 0.0) && pl.P > 0) {
     if ((e = pa::launch_fill_value(dt, v, pl.P, 1.0 / std::sqrt((double)pl.P), st)) != hipSuccess) return e;
     for (int it = 0; it < S.power_iters; ++it) {
-      if ((e = pa::launch_forward(pl, v, q, nullptr, st)) != hipSuccess) return e;
+      if ((e = pa::launch_forward(pl, v, q, nullptr, fwd, st)) != hipSuccess) return e;
       if (pl.bp_grid > 0 && (e = pa::launch_adjoint(pl, q, s, nullptr, st)) != hipSuccess) return e;
       if ((e = pa::launch_norm2(dt, s, pl.P, part_n, st)) != hipSuccess) return e;
       if ((e = pa::launch_pw_scale(dt, v, s, pl.P, part_n, sigma2, st)) != hipSuccess) return e;
@@ -265,7 +268,7 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
     void* zn = zb[(k + 1) & 1];
     // r = y - A z ; s = A^T r - lambda z with the partials of ||z||^2 (the
     // epilogue's step is the zero that init_r writes, so z is unchanged)
-    if ((e = pa::launch_forward(pl, z, q, nullptr, st)) != hipSuccess) return e;
+    if ((e = pa::launch_forward(pl, z, q, nullptr, fwd, st)) != hipSuccess) return e;
     if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
     if (pl.bp_grid == 0) {
       if ((e = pa::launch_fill(PA_F64, part_s, gbp, st)) != hipSuccess) return e;
@@ -285,7 +288,7 @@ hipError_t enqueue_fista(const FiSolve& S, hipStream_t st) {
     t = t1;
   }
   // the objective at the final iterate
-  if ((e = pa::launch_forward(pl, S.x, q, nullptr, st)) != hipSuccess) return e;
+  if ((e = pa::launch_forward(pl, S.x, q, nullptr, fwd, st)) != hipSuccess) return e;
   if ((e = pa::launch_init_r(dt, r, S.y, q, pl.M, part_r, status, alpha0, st)) != hipSuccess) return e;
   if ((e = pa::launch_fista_terms(dt, S.x, S.nx, S.ny, pl.P, S.beta, S.eps, part_n, part_tv, part_l1, st)) !=
       hipSuccess)
@@ -518,7 +521,36 @@ pa_status pa_forward(const pa_geometry* g, pa_dtype dtype, const void* x, void* 
   if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
   if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
   if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
-  PA_HIP(pa::launch_forward(pl, x, y, nullptr, static_cast<hipStream_t>(hip_stream)), "forward kernel");
+  PA_HIP(pa::launch_forward(pl, x, y, nullptr, nullptr, static_cast<hipStream_t>(hip_stream)), "forward kernel");
+  return PA_OK;
+}
+
+size_t pa_forward_workspace_bytes(const pa_geometry* g, pa_dtype dtype) {
+  g_err.clear();
+  pa::Plan pl;
+  if (plan_or_fail(g, dtype, &pl) != PA_OK) return 0;
+  return pl.two_pass ? pl.fwd_scratch : 0;
+}
+
+pa_status pa_forward_ws(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* workspace,
+                        size_t workspace_bytes, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = plan_or_fail(g, dtype, &pl);
+  if (st != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  const size_t need = pl.two_pass ? pl.fwd_scratch : 0;
+  if (need > 0) {
+    if (!workspace) return set_err(PA_ERR_WORKSPACE, "workspace is NULL");
+    if (!aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    if (workspace_bytes < need) return set_err(PA_ERR_WORKSPACE, "workspace smaller than pa_forward_workspace_bytes()");
+    if (overlap(workspace, need, x, pl.P * pl.elem) || overlap(workspace, need, y, pl.M * pl.elem))
+      return set_err(PA_ERR_INVALID_ARGUMENT, "workspace overlaps x or y");
+  }
+  PA_HIP(pa::launch_forward(pl, x, y, nullptr, need > 0 ? workspace : nullptr, static_cast<hipStream_t>(hip_stream)),
+         "forward kernels");
   return PA_OK;
 }
 
@@ -860,7 +892,26 @@ pa_status pa_batch_stop_iterations(const pa_batch* b, const void* workspace, int
   return any ? PA_ERR_BREAKDOWN : PA_OK;
 }
 
-pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, void* hip_stream, pa_tuning* out) {
+size_t pa_autotune_workspace_bytes(const pa_geometry* g, pa_dtype dtype) {
+  g_err.clear();
+  pa::Plan base;
+  if (plan_or_fail(g, dtype, &base) != PA_OK) return 0;
+  size_t n = 0;
+  if (dtype == PA_F32) {
+    int cand[8][3];
+    const int nc = pa::fwd_tile_candidates(base.ndim, cand, 8);
+    for (int i = 0; i < nc; ++i) {
+      pa::Tuning t{0, 0, 3, {cand[i][0], cand[i][1], cand[i][2]}};
+      pa::Plan pl;
+      std::string msg;
+      if (pa::make_plan(g, dtype, &pl, &msg, &t) == PA_OK && pl.two_pass) n = std::max(n, pl.fwd_scratch);
+    }
+  }
+  return n;
+}
+
+pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, void* workspace, size_t workspace_bytes,
+                      void* hip_stream, pa_tuning* out) {
   g_err.clear();
   pa::Plan base;
   pa_status st = plan_or_fail(g, dtype, &base);
@@ -868,6 +919,10 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
   if ((st = check_vec(x, base.P, base.elem, "x")) != PA_OK) return st;
   if ((st = check_vec(y, base.M, base.elem, "y")) != PA_OK) return st;
   if (overlap(x, base.P * base.elem, y, base.M * base.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  if (workspace && !aligned(workspace, 256)) return set_err(PA_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (workspace && (overlap(workspace, workspace_bytes, x, base.P * base.elem) ||
+                    overlap(workspace, workspace_bytes, y, base.M * base.elem)))
+    return set_err(PA_ERR_INVALID_ARGUMENT, "workspace overlaps x or y");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   PA_HIP(hipEventCreate(&e0), "hipEventCreate");
@@ -895,7 +950,7 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
     *us = best;
     return hipSuccess;
   };
-  pa::Tuning best{0, 0, 0};
+  pa::Tuning best{0, 0, 0, {0, 0, 0}};
   float best_f = 3.0e38f, best_a = 3.0e38f;
   hipError_t err = hipSuccess;
   // the forward kernel skips all-zero tiles, so time it on a full image
@@ -909,18 +964,39 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
     for (int mode = 1; mode <= nmode && err == hipSuccess; ++mode) {
       int last_seg = -1;
       for (int i = 0; i < nc && err == hipSuccess; ++i) {
-        pa::Tuning t{cand[i], 0, dtype == PA_F64 ? 0 : mode};
+        pa::Tuning t{cand[i], 0, dtype == PA_F64 ? 0 : mode, {0, 0, 0}};
         pa::Plan pl;
         std::string msg;
         if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK) continue;
         if (pl.op.fseg == last_seg) continue;  // clipped to the same segment as the previous candidate
         last_seg = pl.op.fseg;
         float us = 0.f;
-        err = time_it([&] { return pa::launch_forward(pl, x, y, nullptr, s); }, &us);
+        err = time_it([&] { return pa::launch_forward(pl, x, y, nullptr, nullptr, s); }, &us);
         if (err == hipSuccess && us < best_f) {
           best_f = us;
           best.fwd_seg = pl.op.fseg;
           best.fwd_mode = t.fwd_mode;
+        }
+      }
+    }
+    // the partial-row method (PA_F32), for forward tiles whose rows fit the workspace
+    if (dtype == PA_F32 && workspace) {
+      int tc[8][3];
+      const int ntc = pa::fwd_tile_candidates(base.ndim, tc, 8);
+      for (int i = 0; i < ntc && err == hipSuccess; ++i) {
+        pa::Tuning t{0, 0, 3, {tc[i][0], tc[i][1], tc[i][2]}};
+        pa::Plan pl;
+        std::string msg;
+        if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK || !pl.two_pass) continue;
+        if (pl.op.msub[0] != tc[i][0] || pl.op.msub[1] != tc[i][1] || pl.op.msub[2] != tc[i][2]) continue;
+        if (pl.fwd_scratch > workspace_bytes) continue;
+        float us = 0.f;
+        err = time_it([&] { return pa::launch_forward(pl, x, y, nullptr, workspace, s); }, &us);
+        if (err == hipSuccess && us < best_f) {
+          best_f = us;
+          best.fwd_seg = pl.op.fseg;
+          best.fwd_mode = 3;
+          for (int a = 0; a < 3; ++a) best.fwd_tile[a] = tc[i][a];
         }
       }
     }
@@ -931,7 +1007,7 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
     const int nc = pa::adj_lds_candidates(cand, 8);
     int last_sc = -1;
     for (int i = 0; i < nc && err == hipSuccess; ++i) {
-      pa::Tuning t{0, (int32_t)cand[i], 0};
+      pa::Tuning t{0, (int32_t)cand[i], 0, {0, 0, 0}};
       pa::Plan pl;
       std::string msg;
       if (pa::make_plan(g, dtype, &pl, &msg, &t) != PA_OK) continue;
@@ -952,10 +1028,39 @@ pa_status pa_autotune(const pa_geometry* g, pa_dtype dtype, void* x, void* y, vo
   if (out) {
     out->fwd_seg = best.fwd_seg;
     out->fwd_mode = best.fwd_mode;
+    for (int a = 0; a < 3; ++a) out->fwd_tile[a] = best.fwd_tile[a];
     out->adj_lds_bytes = best.adj_lds;
     out->fwd_us = best_f < 3.0e38f ? best_f : 0.0;
     out->adj_us = best_a < 3.0e38f ? best_a : 0.0;
   }
+  return PA_OK;
+}
+
+pa_status pa_tuning_set(const pa_geometry* g, pa_dtype dtype, const pa_tuning* t) {
+  g_err.clear();
+  if (!t) return set_err(PA_ERR_INVALID_ARGUMENT, "tuning pointer is NULL");
+  pa::Plan base;
+  pa_status st = plan_or_fail(g, dtype, &base);
+  if (st != PA_OK) return st;
+  if (t->fwd_seg < 0 || t->adj_lds_bytes < 0 || t->fwd_mode < 0 || t->fwd_mode > 3)
+    return set_err(PA_ERR_INVALID_ARGUMENT, "fwd_seg, adj_lds_bytes >= 0 and fwd_mode in 0..3 required");
+  if (t->fwd_mode == 3) {
+    if (dtype != PA_F32) return set_err(PA_ERR_UNSUPPORTED, "fwd_mode 3 (partial rows) is PA_F32 only");
+    for (int a = 0; a < 3; ++a)
+      if (t->fwd_tile[a] < 1) return set_err(PA_ERR_INVALID_ARGUMENT, "fwd_mode 3 needs fwd_tile >= 1 on every axis");
+  }
+  if (t->fwd_mode == 2 && dtype == PA_F64) return set_err(PA_ERR_UNSUPPORTED, "PA_F64 has fwd_mode 0 only");
+  pa::Tuning tu{t->fwd_seg, t->adj_lds_bytes, t->fwd_mode, {t->fwd_tile[0], t->fwd_tile[1], t->fwd_tile[2]}};
+  pa::Plan pl;
+  std::string msg;
+  if ((st = pa::make_plan(g, dtype, &pl, &msg, &tu)) != PA_OK) return set_err(st, msg);
+  // every requested choice must be the one the planner takes
+  if (t->fwd_seg > 0 && pl.fp_grid > 0 && pl.op.fseg != std::min<int32_t>(t->fwd_seg, g->n_samples))
+    return set_err(PA_ERR_UNSUPPORTED, "fwd_seg: the forward histogram does not fit in LDS");
+  if (t->fwd_mode == 3 && (!pl.two_pass || pl.op.msub[0] != t->fwd_tile[0] || pl.op.msub[1] != t->fwd_tile[1] ||
+                           pl.op.msub[2] != t->fwd_tile[2]))
+    return set_err(PA_ERR_UNSUPPORTED, "fwd_tile: the partial-row tile does not fit this geometry");
+  pa::tune_store(g, dtype, tu);
   return PA_OK;
 }
 

@@ -21,9 +21,11 @@ struct CgArgs {
 hipError_t launch_fill(pa_dtype dt, void* p, int64_t n, hipStream_t st);
 // x := A^T y (or the CGLS epilogue when cg != nullptr)
 hipError_t launch_adjoint(const Plan& pl, const void* y, void* x, const CgArgs* cg, hipStream_t st);
-// y := A x; when part_q is not NULL it receives max(plan.fp_grid, 1) FP64
-// partial sums of ||y||^2
-hipError_t launch_forward(const Plan& pl, const void* x, void* y, double* part_q, hipStream_t st);
+// y := A x; when part_q is not NULL it receives the FP64 partial sums of
+// ||y||^2 (max(plan.fp_grid, 1) of them, or plan.gather_grid through partial
+// rows).  With plan.two_pass and a scratch of plan.fwd_scratch bytes the
+// partial-row method runs; otherwise the sensor-major one.
+hipError_t launch_forward(const Plan& pl, const void* x, void* y, double* part_q, void* scratch, hipStream_t st);
 hipError_t launch_init_r(pa_dtype dt, void* r, const void* y, const void* q, int64_t m, double* part_r, int* status,
                          double* alpha0, hipStream_t st);
 hipError_t launch_upd_r(pa_dtype dt, void* r, const void* q, int64_t m, const double* part_q, int gq, const double* part_p,

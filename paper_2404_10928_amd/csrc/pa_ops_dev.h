@@ -197,24 +197,50 @@ static_assert(sizeof(Near32) == 32, "Near32 layout");
 // (the near radius covers r_min), so CLAMP only chooses whether the max
 // instruction is emitted: both choices give the same taps, and the kernels
 // use whichever schedules better (measured: A without, A^T with).
-template <int ND, bool FRAC, int ESZ, bool CLAMP = true>
-__device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, int& kbyte, float& f, float& wt) {
+template <int ND, bool FRAC, int ESZ, bool CLAMP, typename C>
+__device__ __forceinline__ void phase32(const C& c, float cmin, float half, const Pix32& px, float t0f, int& kbyte,
+                                        float& f, float& wt) {
   float t = px.q + c.E;
   float num = fmaf(px.oy, c.DY2, t);
   if (ND == 3) num = fmaf(px.oz, c.DZ2, num);
   num = fmaf(px.ox, c.DX2, num);
-  if (CLAMP) num = fmaxf(num, c.CMIN);
+  if (CLAMP) num = fmaxf(num, cmin);
   const float R2 = num + c.KR2;
   const float w = __builtin_amdgcn_rsqf(R2);
   const float da = fmaf(R2, w, c.KRN);       // R - kr, FP32 estimate
   const float r1 = fmaf(c.KR2N, da, num);
   const float r = fmaf(-da, da, r1);         // num - da (da + 2 kr)
-  wt = c.HALF * w;                           // 1 / (2R)
+  wt = half * w;                             // 1 / (2R)
   float d = fmaf(r, wt, da);                 // Newton-corrected R - kr
   if (FRAC) d = d - t0f;
   f = __builtin_amdgcn_fractf(d);           // d - floor(d), exact
   kbyte = (int)floorf(d) * ESZ + c.BASE;
 }
+
+template <int ND, bool FRAC, int ESZ, bool CLAMP = true>
+__device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, int& kbyte, float& f, float& wt) {
+  phase32<ND, FRAC, ESZ, CLAMP>(c, c.CMIN, c.HALF, px, t0f, kbyte, f, wt);
+}
+
+// Forward operator: far pairs only (active, no clamp reached), weight 1 / (2R).
+template <int ND, bool FRAC, int ESZ, bool CLAMP = false>
+__device__ __forceinline__ void phase(const FpSC32& c, const Pix32& px, float t0f, int& kbyte, float& f, float& wt) {
+  phase32<ND, FRAC, ESZ, false>(c, 0.f, 0.5f, px, t0f, kbyte, f, wt);
+}
+
+__device__ __forceinline__ FpSC32 fp_sc(const SC32& c) {
+  FpSC32 o;
+  o.E = c.E;
+  o.DX2 = c.DX2;
+  o.DY2 = c.DY2;
+  o.DZ2 = c.DZ2;
+  o.KRN = c.KRN;
+  o.KR2N = c.KR2N;
+  o.KR2 = c.KR2;
+  o.BASE = c.BASE;
+  return o;
+}
+__device__ __forceinline__ SC64 fp_sc(const SC64& c) { return c; }
 
 // FP32 kernels, near pairs: delay and weight from FP64 coordinates.
 template <int ND, bool FRAC, int ESZ>
@@ -514,7 +540,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
 // the segment (plus a window's margin, since a tile reaching the segment may
 // also reach its neighbours) and the tiles that reach it are compacted into
 // an LDS list, in tile order, with their per-(tile, sensor) constants.  Wave w
-// then takes groups of kFwdGroup consecutive list entries, groups w, w+4, ...:
+// then takes groups of G consecutive list entries, groups w, w+4, ...:
 // the sensor and tiles are uniform across the wave, so the delay constants
 // are wave-uniform LDS reads, and each lane keeps its four pixels' offsets
 // from a tile centre in registers for the whole kernel.  The next group's x
@@ -535,11 +561,12 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
 template <typename T, typename PH, int ND, bool FRAC, bool FIX>
 __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, const T* __restrict__ x,
                                         T* __restrict__ y, double* __restrict__ part_q) {
-  using SC = typename SCOf<PH>::type;
+  using SCA = typename SCOf<PH>::type;    // the adjoint's constants, made by the same function
+  using SC = typename std::conditional<sizeof(PH) == 4, FpSC32, SC64>::type;
   using PX = typename PixOf<PH>::type;
   constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
   constexpr int PPL = TX * TY * TZ / 64;   // pixels per lane per base tile
-  constexpr int G = kFwdGroup;
+  constexpr int G = kFwdGroupMax / 2;
   constexpr bool P32 = sizeof(PH) == 4;
   constexpr int HB = FIX ? 4 : 8;          // bytes per bin of the rows the taps go to
   static_assert(P32 || !FIX, "fixed-point rows are for FP32 delay arithmetic");
@@ -548,7 +575,8 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
   SC* lst = reinterpret_cast<SC*>(smem + L.lst);
   FpTile* ltab = reinterpret_cast<FpTile*>(smem + L.ltab);
   __shared__ double red[4];
-  __shared__ int cnt[4];
+  __shared__ int cnt[4], ccnt[4];
+  __shared__ int ctile[kFwdList];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -565,6 +593,20 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
   const int rbase = FIX ? (int)(size_t)irow : (int)(size_t)hist;  // LDS byte address of this wave's tap row
   double sp[3];
   sensor_pos<ND>(P, s, sp);
+  // FP32 copies for the candidate test: tile-centre grid, sensor, t0 and the
+  // base tile's half-diagonal plus a margin for FP32 rounding (sample units)
+  float fc_org[3], fc_step[3], fsp[3];
+  {
+    const int T3[3] = {TX, TY, TZ};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      fc_org[a] = (float)(P.org[a] + 0.5 * (T3[a] - 1) * P.hs);
+      fc_step[a] = (float)(T3[a] * P.hs);
+      fsp[a] = (float)sp[a];
+    }
+  }
+  const float fT0 = (float)((double)P.t0i + P.t0fd);
+  const float f_hd = (float)(0.5 * P.hs * sqrt((double)((TX - 1) * (TX - 1) + (TY - 1) * (TY - 1) + (TZ - 1) * (TZ - 1)))) + 2.f;
   // this lane's pixels of a base tile: p = lane + 64 q
   PX px[PPL];
   int poff[PPL], plim[PPL];
@@ -581,8 +623,34 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
   constexpr int kFull = TX | TY << 8 | TZ << 16;  // FpTile::lim of a tile inside the image
 
   for (int c0 = 0; c0 < P.n_tiles; c0 += kFwdList) {
-    // ---- list the tiles of this round whose window reaches the segment
-    const int t = c0 + tid;
+    // ---- list the tiles of this round whose window reaches the segment.
+    // A cheap FP32 test on the tile centre's distance first (a superset of
+    // the tiles that reach the segment), then the exact FP64 window only for
+    // the candidates, compacted onto the first lanes.
+    int t = c0 + tid;
+    bool cand = false;
+    if (t < P.n_tiles) {
+      const int cx = t % P.ntile[0];
+      const int cy = (t / P.ntile[0]) % P.ntile[1];
+      const int cz = t / (P.ntile[0] * P.ntile[1]);
+      const float dx = fc_org[0] + (float)cx * fc_step[0] - fsp[0];
+      const float dy = fc_org[1] + (float)cy * fc_step[1] - fsp[1];
+      const float dz = ND == 3 ? fc_org[2] + (float)cz * fc_step[2] - fsp[2] : 0.f;
+      const float dc = __builtin_sqrtf(dx * dx + dy * dy + dz * dz) - fT0;
+      cand = dc - f_hd < (float)(k0 + P.fseg + 4) && dc + (float)P.wp > (float)(k0 - 4);
+    }
+    {
+      const unsigned long long cb = __ballot(cand);
+      __syncthreads();  // the previous round's list and candidates have been consumed
+      if (lane == 0) ccnt[wave] = __popcll(cb);
+      __syncthreads();
+      int cbefore = 0;
+      for (int w = 0; w < wave; ++w) cbefore += ccnt[w];
+      if (cand) ctile[cbefore + __popcll(cb & lt_mask)] = t;
+      __syncthreads();
+    }
+    const int nc = ccnt[0] + ccnt[1] + ccnt[2] + ccnt[3];
+    t = tid < nc ? ctile[tid] : P.n_tiles;
     bool take = false;
     int kl = 0;
     double ref[3], dmin = 0.0;
@@ -605,7 +673,6 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
       take = in_trace && kl < k0 + P.fseg && kl + P.wp > k0;
     }
     const unsigned long long bal = __ballot(take);
-    __syncthreads();  // the previous round's list has been consumed
     if (lane == 0) cnt[wave] = __popcll(bal);
     __syncthreads();
     int before = 0;
@@ -613,40 +680,50 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
     const int nl = cnt[0] + cnt[1] + cnt[2] + cnt[3];
     if (take) {
       const int pos = before + __popcll(bal & lt_mask);
-      SC c;
+      SCA c;
       make_sc<ND>(P, ref, sp, hlo, 0, HB, true, c);  // tap bins relative to the histogram
-      lst[pos] = c;
+      lst[pos] = fp_sc(c);
       FpTile ft;
-      ft.tile = t;
       ft.off = kl - hlo;
       ft.xoff = ((bz * TZ) * P.ny + by * TY) * P.nx + bx * TX;
-      ft.lim = min(TX, P.nx - bx * TX) | min(TY, P.ny - by * TY) << 8 | min(TZ, P.nz - bz * TZ) << 16;
+      ft.lim = min(TX, P.nx - bx * TX) | min(TY, P.ny - by * TY) << 8 | min(TZ, P.nz - bz * TZ) << 16 |
+               ((P32 && is_near(P, ref, sp)) ? kFpNear : 0);
       ft.ib = (float)(0.5 / dmin);
-      ft.near = (P32 && is_near(P, ref, sp)) ? 1 : 0;
-      ft.pad[0] = ft.pad[1] = 0;
       ltab[pos] = ft;
+    }
+    if (tid >= nl && tid < (nl + kFwdGroupMax - 1) / kFwdGroupMax * kFwdGroupMax) {  // pad the list to whole groups
+      FpTile ft;
+      ft.off = 0;
+      ft.xoff = 0;
+      ft.lim = 0;
+      ft.ib = 0.f;
+      ltab[tid] = ft;
     }
     __syncthreads();
 
     // ---- scatter: wave w takes groups w, w+4, ... of G consecutive entries
     const int ngroups = (nl + G - 1) / G;
     T xn[G][PPL];
+    // (the list is padded to whole groups with entries of no pixels, lim = 0,
+    // so the loads need no bounds test on the list; partial tiles load their
+    // first pixel in place of pixels outside the image and zero it)
     auto load_x = [&](int g0, T (&xv)[G][PPL]) {
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int j = g0 * G + u;
-        const int xoff = __builtin_amdgcn_readfirstlane(j < nl ? ltab[j].xoff : 0);
-        const int lim = __builtin_amdgcn_readfirstlane(j < nl ? ltab[j].lim : 0);
+        const int xoff = __builtin_amdgcn_readfirstlane(ltab[j].xoff);
+        const int lim = __builtin_amdgcn_readfirstlane(ltab[j].lim) & (kFpNear - 1);
         const T* __restrict__ xb = x + xoff;   // wave-uniform base, per-lane 32-bit offsets
         if (lim == kFull) {
 #pragma unroll
           for (int q = 0; q < PPL; ++q) xv[u][q] = xb[(unsigned)poff[q]];
-        } else {  // a tile at the image edge (or past the list's end: lim = 0)
+        } else {
 #pragma unroll
           for (int q = 0; q < PPL; ++q) {
             const bool in = (plim[q] & 0xff) < (lim & 0xff) && ((plim[q] >> 8) & 0xff) < ((lim >> 8) & 0xff) &&
                             (plim[q] >> 16) < (lim >> 16);
-            xv[u][q] = in ? xb[(unsigned)poff[q]] : (T)0;
+            const T v = xb[in ? (unsigned)poff[q] : 0u];
+            xv[u][q] = in ? v : (T)0;
           }
         }
       }
@@ -685,26 +762,42 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
         // (the kernels are built without NaN semantics, so non-finite values
         // are recognised from their exponent bits)
         if ((__float_as_uint(bound) & 0x7f800000u) == 0x7f800000u) {
-          for (int e = rlo + lane; e < rhi; e += 64) hist[e] = __uint_as_float(0x7fc00000u);
+          for (int e = rlo + lane; e < rhi; e += 64)   // stored as bits, out of reach of NaN folding
+            reinterpret_cast<long long*>(hist)[e] = 0x7ff8000000000000ll;
           continue;  // a NaN or infinite x (or a sum beyond float): the group's windows become NaN
         }
         if (bound == 0.0f) continue;  // all-zero tiles: nothing to add
-        scl = 1073741824.0f * __builtin_amdgcn_rcpf(bound);
-        inv = 1.0 / (double)scl;
+        float b = bound;
+        double post = 1.0;
+        if (b < 0x1p-60f) {
+          // tiny x (below ~1e-18): scale the group's values by an exact power
+          // of two first, so 2^30 / bound stays finite and the fixed point
+          // keeps its full range; the rows are scaled back on the way out
+          const int e = min(120, -ilogbf(b));
+          const float sx = ldexpf(1.0f, e);
+#pragma unroll
+          for (int u = 0; u < G; ++u)
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) xv[u][q] = xv[u][q] * (T)sx;
+          b *= sx;
+          post = ldexp(1.0, -e);
+        }
+        scl = 1073741824.0f * __builtin_amdgcn_rcpf(b);
+        inv = post / (double)scl;
       }
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         if (u >= nu) break;
         SC c = lst[j0 + u];
         c.BASE += rbase;
-        const int near = __builtin_amdgcn_readfirstlane(ltab[j0 + u].near);
+        const int near = __builtin_amdgcn_readfirstlane(ltab[j0 + u].lim) & kFpNear;
         if (!P32 || near == 0) {
 #pragma unroll
           for (int q = 0; q < PPL; ++q) {
             int kb;
             PH f, wt;
-            phase<ND, FRAC, HB, false>(c, px[q], t0f, kb, f, wt);
             if constexpr (FIX) {
+              phase<ND, FRAC, HB, false>(c, px[q], t0f, kb, f, wt);
               const float vs = (wt * (float)xv[u][q]) * scl;
               const int it = round_i(vs);
               const int i1 = round_i(vs * f);
@@ -712,6 +805,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
               lds_add(bin, it - i1);
               lds_add(bin + 1, i1);
             } else {
+              phase<ND, FRAC, HB, false>(c, px[q], t0f, kb, f, wt);
               const double v = (double)wt * (double)xv[u][q];
               const double a1 = v * (double)f;
               double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
@@ -721,9 +815,10 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
           }
         } else if constexpr (P32) {
           // sensor among or near the tile's pixels: delays from FP64 coordinates
-          const int tb = ltab[j0 + u].tile;
+          const int xo = ltab[j0 + u].xoff;
+          const int pl = P.nx * P.ny;
           double rf[3];
-          tile_ref<ND>(P, tb % P.ntile[0], (tb / P.ntile[0]) % P.ntile[1], tb / (P.ntile[0] * P.ntile[1]), rf);
+          tile_ref<ND>(P, (xo % P.nx) / TX, ((xo % pl) / P.nx) / TY, (xo / pl) / TZ, rf);
           Near32 nn;
           nn.DX = rf[0] - sp[0];
           nn.DY = rf[1] - sp[1];
@@ -789,6 +884,338 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
   if (part_q) {
     qq = block_sum(qq, red);
     if (tid == 0) part_q[pidx] = qq;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A through partial rows (PA_F32 with a workspace), pass 1: one work-group
+// per (forward tile, chunk of 64 sensors); lane =
+// sensor, wave w walks base tiles w, w+4, ... of the forward tile (or, with
+// fewer than four base tiles, a quarter or half of one) one pixel at a time
+// (the pixel is uniform across the wave).  Each lane scatters its two
+// taps into its own sensor's LDS histogram row, so the lanes of one ds_add
+// never collide on an address.  The rows are then written out with plain
+// coalesced stores, with the first sample of each row in a table.
+template <int ND, bool FRAC>
+__device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* __restrict__ x, float* __restrict__ rows,
+                                         int* __restrict__ klo_tab) {
+  using T = float;
+  using SC = SC32;
+  using PX = Pix32;
+  constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
+  constexpr int NS = kSensorsPerFwdBlock;
+  constexpr bool F32 = true;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Fp2Layout L = fp2_layout(P.wpa, P.nsub);
+  // Histogram bins.  FP64 kernels add doubles.  FP32 kernels add 32-bit
+  // fixed-point integers (LDS float adds are slow on gfx950, integer adds are
+  // not): lane s scales its taps by 2^30 / B_s, where B_s bounds the sum of
+  // |tap| over the whole forward tile, so no bin can overflow; integer sums
+  // do not depend on their order, and each row is converted back once, when
+  // it is written out.
+  using H = typename std::conditional<F32, int, double>::type;
+  constexpr int HB = (int)sizeof(H);
+  H* hist = reinterpret_cast<H*>(smem + L.hist);
+  PX* pixtab = reinterpret_cast<PX*>(smem + L.pixtab);
+  T* xs = reinterpret_cast<T*>(smem + L.xs);
+  int* klo_a = reinterpret_cast<int*>(smem + L.klo);
+  double* inv_a = reinterpret_cast<double*>(smem + L.inv);
+  __shared__ double red[4];
+
+  const int chunk = b % P.n_chunks;
+  const int at = b / P.n_chunks;
+  const int ax = at % P.natile[0];
+  const int ay = (at / P.natile[0]) % P.natile[1];
+  const int az = at / (P.natile[0] * P.natile[1]);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+  const int s = chunk * NS + lane;
+  const bool s_ok = s < P.S;
+
+  // pixel offsets of a base tile (same for every base tile) and the forward tile's x values
+  {
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    make_pix<ND>(P, lx, ly, lz, pixtab[tid]);
+    for (int m = 0; m < P.nsub; ++m) {
+      const int bx = ax * P.msub[0] + m % P.msub[0];
+      const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
+      const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
+      const int ix = bx * TX + lx, iy = by * TY + ly, iz = bz * TZ + lz;
+      T v = 0;
+      if (ix < P.nx && iy < P.ny && iz < P.nz) v = x[((size_t)iz * P.ny + iy) * P.nx + ix];
+      xs[m * kBlock + tid] = v;
+    }
+  }
+  // this lane's sensor and its window over the whole forward tile
+  double sp[3];
+  sensor_pos<ND>(P, s_ok ? s : P.S - 1, sp);
+  bool in_trace;
+  int kl;
+  {
+    double lo[3], hi[3];
+    const int T3[3] = {TX, TY, TZ};
+    double r0[3];
+    tile_ref<ND>(P, ax * P.msub[0], ay * P.msub[1], az * P.msub[2], r0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
+      hi[a] = lo[a] + (P.msub[a] * T3[a] - 1) * P.hs;
+    }
+    if (ND == 2) { lo[2] = 0.0; hi[2] = 0.0; }
+    kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wpa);
+  }
+  const bool active = s_ok && in_trace;
+  // Fixed-point scale: a tap of pixel p in base tile m is at most
+  // |x_p| / (2 dmin_m), dmin_m being the distance from this lane's sensor to
+  // base tile m (clamped at r_min), so B_s = sum_m (sum_{p in m} |x_p|) /
+  // (2 dmin_m) bounds every partial sum of the row.
+  float scl = 0.f;
+  if constexpr (F32) {
+    double* sa_m = reinterpret_cast<double*>(smem + L.inv) + NS;  // [nsub][4] per-wave partials
+    for (int m = 0; m < P.nsub; ++m) {
+      double v = fabs((double)xs[m * kBlock + tid]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) sa_m[m * 4 + wave] = v;
+    }
+    __syncthreads();
+    // Tiny x (the forward tile's sum below ~1e-18): scale the staged values
+    // by an exact power of two, so 2^30 / B_s stays finite and the fixed
+    // point keeps its full range; the rows are scaled back on the way out.
+    // (The sum is the same in every lane, so the branch is uniform.)
+    double tsum = 0.0;
+    for (int m = 0; m < 4 * P.nsub; ++m) tsum += sa_m[m];
+    double post = 1.0, pre = 1.0;
+    if (tsum > 0.0 && tsum < 0x1p-60) {
+      const int e = min(120, -ilogb(tsum));
+      const float sx = ldexpf(1.0f, e);
+      for (int i = tid; i < P.nsub * kBlock; i += kBlock) xs[i] *= sx;
+      __syncthreads();
+      pre = (double)sx;
+      post = ldexp(1.0, -e);
+    }
+    double bound = 0.0;
+    for (int m = 0; m < P.nsub; ++m) {
+      const double sa = pre * ((sa_m[m * 4 + 0] + sa_m[m * 4 + 1]) + (sa_m[m * 4 + 2] + sa_m[m * 4 + 3]));
+      if (sa == 0.0) continue;
+      const int bx = ax * P.msub[0] + m % P.msub[0];
+      const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
+      const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
+      double r0[3], lo[3], hi[3];
+      tile_ref<ND>(P, bx, by, bz, r0);
+      const int T3[3] = {TX, TY, TZ};
+      double d2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < ND; ++a) {
+        lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
+        hi[a] = r0[a] + 0.5 * (T3[a] - 1) * P.hs;
+        const double e = fmax(fmax(lo[a] - sp[a], sp[a] - hi[a]), 0.0);
+        d2 += e * e;
+      }
+      bound += sa * (0.5 / fmax(sqrt(d2), P.rmin));
+    }
+    bound *= 1.0 + 1.0 / 1024.0;
+    // A NaN or infinite x makes the bound non-finite (recognised from its
+    // exponent bits: the kernels are built without NaN semantics); the row
+    // then gets a NaN scale, so its traces come out NaN instead of zero.
+    const bool bad = (__double_as_longlong(bound) & 0x7ff0000000000000ll) == 0x7ff0000000000000ll;
+    if (!bad && bound > 0.0 && bound < 1e300) scl = (float)(1073741824.0 / bound);
+    if (wave == 0) {
+      // (selected as integer bits: under the no-NaN build flags a NaN operand
+      // of a floating-point select may be folded away)
+      const long long v = __double_as_longlong(scl > 0.f ? post / (double)scl : 0.0);
+      reinterpret_cast<long long*>(inv_a)[lane] = bad ? 0x7ff8000000000000ll : v;
+    }
+  }
+  if (wave == 0) klo_a[lane] = active ? kl : P.K + 8;
+  for (int e = tid; e < NS * P.wpa; e += kBlock) hist[e] = 0;
+  __syncthreads();
+
+  const float t0f = P.t0f;
+  // Work items: (base tile m, part).  With fewer than four base tiles per
+  // forward tile the waves split each tile's pixels into `parts` ranges.
+  const int parts = P.nsub >= 4 ? 1 : 4 / P.nsub;
+  for (int item = wave; item < P.nsub * parts; item += 4) {
+    const int m = item / parts;
+    const int part = item - m * parts;
+    const int bx = ax * P.msub[0] + m % P.msub[0];
+    const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
+    const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
+    const int nlx = __builtin_amdgcn_readfirstlane(min(TX, P.nx - bx * TX));
+    const int nly = __builtin_amdgcn_readfirstlane(min(TY, P.ny - by * TY));
+    const int nlz = __builtin_amdgcn_readfirstlane(min(TZ, P.nz - bz * TZ));
+    if (nlx <= 0 || nly <= 0 || nlz <= 0) continue;
+    double ref[3];
+    tile_ref<ND>(P, bx, by, bz, ref);
+    // Near (tile, sensor) pairs take benign zero-weight constants here and
+    // are added afterwards, one sensor at a time with one pixel per lane, so
+    // the wave never runs the FP64 delay path for all of its pixels.
+    const bool near = F32 && active && is_near(P, ref, sp);
+    SC c;
+    make_sc<ND>(P, ref, sp, kl, lane * P.wpa, HB, active && !near, c);
+    c.BASE += (int)(size_t)hist;  // absolute LDS byte address
+    asm volatile("" : "+v"(c.BASE));  // keep "k * HB + BASE" a single shift-add
+    const T* xm = xs + m * kBlock;
+    // Every pixel of the base tile, in order, four per step.  Pixels beyond
+    // the image edge have x = 0 (and taps inside the window), so they add
+    // zeros.  The next four pixels' constants are read before this step's
+    // LDS adds are issued, so the adds never hold up the reads (the last
+    // step reads four entries past the range, into the arrays' slack); two
+    // register sets alternate, and the pixel index lives in a VGPR so the
+    // reads take immediate offsets.
+    constexpr int NPIX = TX * TY * TZ;
+    static_assert(NPIX % 32 == 0, "eight pixels per loop trip and up to four parts");
+    const int p_lo = part * (NPIX / parts);
+    const int p_hi = p_lo + NPIX / parts;
+    int vo = p_lo;
+    asm volatile("" : "+v"(vo));
+    PX pa_[4], pb_[4];
+    T xa_[4], xb_[4];
+    auto load4 = [&](PX (&pp)[4], T (&xx)[4]) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        pp[j] = pixtab[vo + j];
+        xx[j] = xm[vo + j];
+      }
+      vo += 4;
+    };
+    auto scatter4 = [&](const PX (&pp)[4], const T (&xx)[4]) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int kb;
+        T f, wt;
+        phase<ND, FRAC, HB, false>(c, pp[j], t0f, kb, f, wt);
+        H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
+        const float vs = (wt * xx[j]) * scl;   // (wt = 1 / (2R) also corrects the delay: not pre-scaled)
+        const int i1 = round_i(vs * f);
+        lds_add(bin, round_i(vs) - i1);
+        lds_add(bin + 1, i1);
+      }
+    };
+    load4(pa_, xa_);
+    for (int p = p_lo; p < p_hi; p += 8) {
+      load4(pb_, xb_);
+      scatter4(pa_, xa_);
+      load4(pa_, xa_);
+      scatter4(pb_, xb_);
+    }
+    if constexpr (F32) {
+      uint64_t nm = part == 0 ? __ballot(near) : 0;  // the near pairs of tile m, once
+      if (nm != 0) {
+        const double rmin2 = P.rmin * P.rmin;
+        // this lane's row base for its own sensor, as the far constants would have it
+        const double kr_l = rint(sqrt((ref[0] - sp[0]) * (ref[0] - sp[0]) + (ref[1] - sp[1]) * (ref[1] - sp[1]) +
+                                      (ref[2] - sp[2]) * (ref[2] - sp[2])));
+        const int base_l = ((int)kr_l - P.t0i - kl + lane * P.wpa) * HB + (int)(size_t)hist;
+        while (nm != 0) {
+          const int j = __builtin_ctzll(nm);
+          nm &= nm - 1;
+          Near32 nn;
+          nn.DX = ref[0] - __shfl(sp[0], j);
+          nn.DY = ref[1] - __shfl(sp[1], j);
+          nn.DZ = ref[2] - __shfl(sp[2], j);
+          nn.KR = __shfl(kr_l, j);
+          const int base = __shfl(base_l, j);
+          const float scl_j = __shfl(scl, j);
+          for (int pix = lane; pix < TX * TY * TZ; pix += 64) {
+            const int lx = pix % TX, ly = (pix / TX) % TY, lz = pix / (TX * TY);
+            if (lx >= nlx || ly >= nly || lz >= nlz) continue;
+            double o[3];
+            pix_offsets<ND>(P, lx, ly, lz, o);
+            int kb;
+            float f, wt;
+            phase_near<ND, FRAC, HB>(nn, o, rmin2, P.t0fd, base, 0.5f, kb, f, wt);
+            const float vs = (wt * xm[pix]) * scl_j;
+            const int it = (int)__builtin_rintf(vs);
+            const int i1 = (int)__builtin_rintf(vs * f);
+            H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
+            lds_add(bin, it - i1);
+            lds_add(bin + 1, i1);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // histogram rows out, row (sensor, forward tile) at ((s * n_atiles) + at) * wpa
+  for (int j = wave; j < NS; j += 4) {
+    const int sj = chunk * NS + j;
+    if (sj >= P.S) break;
+    T* row = rows + ((size_t)sj * P.n_atiles + at) * P.wpa;
+    const double inv = inv_a[j];
+    for (int i = lane; i < P.wpa; i += 64) row[i] = (T)((double)hist[j * P.wpa + i] * inv);
+  }
+  if (wave == 0 && s_ok) klo_tab[(size_t)s * P.n_atiles + at] = klo_a[lane];
+}
+
+// A through partial rows, pass 2: one work-group per (sensor, segment of kseg <= 256 samples),
+// one sample per lane.  Each wave scans the window starts of the sensor's
+// forward tiles, 64 at a time, picks by ballot the tiles whose row window
+// overlaps its own 64 samples, and every lane adds its sample of those rows,
+// in increasing tile order, in FP64 (kGatherLoads loads in flight, the next 64
+// window starts prefetched); then the work-group scales, writes y and forms
+// the FP64 partial of ||y||^2.  No atomics: the result is the same on every
+// run.  Rows and window starts are sensor-major, so one sensor's rows are
+// contiguous.
+constexpr int kGatherLoads = 16;
+
+__device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx, const float* __restrict__ rows,
+                                            const int* __restrict__ klo_tab, float* __restrict__ y,
+                                            double* __restrict__ part_q) {
+  using T = float;
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int s = blk / P.nseg;
+  const int seg = blk - s * P.nseg;
+  const int k0 = seg * P.kseg;
+  const int kn = min(P.kseg, P.K - k0);
+  const int k = k0 + tid;
+  const bool k_ok = tid < kn;
+  const int* kt = klo_tab + (size_t)s * P.n_atiles;
+  const T* srow = rows + (size_t)s * P.n_atiles * P.wpa;
+  const int wlo = k0 + wave * 64, whi = min(k0 + kn, wlo + 64);  // this wave's samples
+  double acc = 0.0;
+  if (wlo < whi) {
+    // window starts of the next 64 tiles are loaded while this chunk's rows are read
+    int kl_next = lane < P.n_atiles ? kt[lane] : 0;
+    for (int c0 = 0; c0 < P.n_atiles; c0 += 64) {
+      const int t = c0 + lane;
+      const int kl = kl_next;
+      const bool ov = t < P.n_atiles && kl < whi && kl + P.wpa > wlo;
+      if (t + 64 < P.n_atiles) kl_next = kt[t + 64];
+      uint64_t m = __ballot(ov);
+      while (m != 0) {
+        double v[kGatherLoads];
+#pragma unroll
+        for (int u = 0; u < kGatherLoads; ++u) {
+          v[u] = 0.0;
+          if (m != 0) {  // wave-uniform
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            const int klb = __builtin_amdgcn_readlane(kl, b);
+            const int j = k - klb;
+            if (k_ok && j >= 0 && j < P.wpa) v[u] = (double)srow[(size_t)(c0 + b) * P.wpa + j];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherLoads; ++u) acc += v[u];
+      }
+    }
+  }
+  const double scale = 2.0 * P.inv_cdt;
+  double q = 0.0;
+  if (k_ok) {
+    const T out = (T)(acc * scale);
+    y[(size_t)s * P.K + k] = out;
+    q = (double)out * (double)out;
+  }
+  if (part_q) {
+    q = block_sum(q, red);
+    if (tid == 0) part_q[pidx] = q;
   }
 }
 

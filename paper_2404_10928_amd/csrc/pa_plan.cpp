@@ -82,9 +82,19 @@ uint64_t tune_epoch() {
 }
 
 int fwd_seg_candidates(int32_t* out, int max) {
-  static const int32_t c[] = {128, 256, 512, 1024};
-  const int n = std::min(4, max);
+  static const int32_t c[] = {128, 256, 384, 512, 640, 768, 1024};
+  const int n = std::min(7, max);
   for (int i = 0; i < n; ++i) out[i] = c[i];
+  return n;
+}
+
+int fwd_tile_candidates(int ndim, int (*out)[3], int max) {
+  static const int c2[][3] = {{1, 1, 1}, {2, 1, 1}, {2, 2, 1}, {4, 2, 1}};
+  static const int c3[][3] = {{1, 1, 1}, {2, 1, 2}, {2, 2, 2}, {2, 2, 4}};
+  const int (*c)[3] = ndim == 2 ? c2 : c3;
+  const int n = std::min(4, max);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) out[i][a] = c[i][a];
   return n;
 }
 
@@ -115,7 +125,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   if (g->sensors && (reinterpret_cast<uintptr_t>(g->sensors) % 8) != 0)
     return fail(msg, PA_ERR_INVALID_ARGUMENT, "sensors must be 8-byte aligned");
 
-  Tuning tuned{0, 0, 0};
+  Tuning tuned{0, 0, 0, {0, 0, 0}};
   if (force) tuned = *force;
   else (void)tune_lookup(g, dtype, &tuned);
 
@@ -175,7 +185,8 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
 
   const size_t elem = pl.elem;
   const bool p32 = phase_is_f32(dtype);
-  const size_t sc_bytes = p32 ? 48 : 64;     // per-(tile, sensor) constants in LDS
+  const size_t sc_bytes = p32 ? 48 : 64;     // per-(tile, sensor) constants in LDS (adjoint)
+  const size_t fsc_bytes = p32 ? sizeof(FpSC32) : 64;  // the same for the forward operator's list
   const size_t near_bytes = p32 ? 32 : 0;    // FP64 sensor vector + reference (FP32 near path)
 
   // Sensors closer than three base-tile half-diagonals to a tile centre take
@@ -217,22 +228,22 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   // the base tiles whose window reaches its segment and scatters their
   // pixels' taps into one FP64 histogram per wave covering the segment plus
   // a window's margin on either side.  The segment is the tuned one, else
-  // the longest of 1024, 512, 256 and 128 samples that still gives at least
-  // 1024 work-groups (four per CU), and never more than the trace.
+  // the longest candidate that still gives at least 512 work-groups (two per
+  // CU), and never more than the trace.
   {
     op.ffix = p32 && tuned.fwd_mode != 2 ? 1 : 0;
     const bool fix = op.ffix != 0;
     auto bins = [&](int32_t seg) { return seg + 2 * op.wp + 2; };
-    auto fits = [&](int32_t seg) { return fp_layout(bins(seg), op.wp, sc_bytes, fix).total <= kLdsMax; };
+    auto fits = [&](int32_t seg) { return fp_layout(bins(seg), op.wp, fsc_bytes, fix).total <= kLdsMax; };
     const int64_t Kp = std::max<int64_t>(g->n_samples, 1);
     int32_t seg = 0;
     if (tuned.fwd_seg > 0 && fits(tuned.fwd_seg)) seg = tuned.fwd_seg;
     if (seg == 0) {
-      int32_t cand[4];
-      const int nc = fwd_seg_candidates(cand, 4);
+      int32_t cand[8];
+      const int nc = fwd_seg_candidates(cand, 8);
       for (int i = nc - 1; i >= 0 && seg == 0; --i) {
         const int64_t wg = (int64_t)g->n_sensors * ((Kp + cand[i] - 1) / cand[i]);
-        if ((wg >= 1024 || i == 0) && fits(cand[i])) seg = cand[i];
+        if ((wg >= 512 || i == 0) && fits(cand[i])) seg = cand[i];
       }
       for (int i = 0; i < nc && seg == 0; ++i)
         if (fits(cand[i])) seg = cand[i];
@@ -241,7 +252,54 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     op.fseg = (int32_t)std::min<int64_t>(seg, Kp);
     op.fnseg = ceil_div(Kp, op.fseg);
     op.fbins = bins(op.fseg);
-    pl.fp_lds = fp_layout(op.fbins, op.wp, sc_bytes, fix).total;
+    pl.fp_lds = fp_layout(op.fbins, op.wp, fsc_bytes, fix).total;
+  }
+
+  // Partial-row forward (PA_F32 only, chosen by autotuning): the histogram
+  // window of one sensor over a forward tile of msub base tiles; the tuned
+  // forward tile if it fits, else the largest candidate whose LDS keeps two
+  // work-groups per CU.  Unavailable (two_pass stays false) if none fits.
+  if (dtype == PA_F32) {
+    auto try_tile = [&](const int* m, size_t budget) {
+      if (!(nd == 3 || m[2] == 1)) return false;
+      double ex = (m[0] * TX - 1) * hs, ey = (m[1] * TY - 1) * hs, ez = (m[2] * TZ - 1) * hs;
+      double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
+      if (diag > 1e6) return false;
+      const int32_t wpa = ((int32_t)std::ceil(diag) + 5) | 1;  // odd stride spreads lanes over LDS banks
+      const int nsub = m[0] * m[1] * m[2];
+      const size_t lds = fp2_layout(wpa, nsub).total;
+      if (lds > budget) return false;
+      for (int a = 0; a < 3; ++a) op.msub[a] = m[a];
+      op.nsub = nsub;
+      op.wpa = wpa;
+      pl.fp2_lds = lds;
+      return true;
+    };
+    bool ok = tuned.fwd_tile[0] > 0 && tuned.fwd_tile[1] > 0 && tuned.fwd_tile[2] > 0 &&
+              try_tile(tuned.fwd_tile, kLdsMax);
+    int cand[4][3];
+    const int nc = fwd_tile_candidates(nd, cand, 4);
+    for (size_t budget : {kLdsPreferredFwd, kLdsMax})
+      for (int ci = nc - 1; ci >= 0 && !ok; --ci) ok = try_tile(cand[ci], budget);
+    if (ok) {
+      for (int a = 0; a < 3; ++a) op.natile[a] = ceil_div(op.ntile[a], op.msub[a]);
+      op.n_atiles = op.natile[0] * op.natile[1] * op.natile[2];
+      op.n_chunks = ceil_div(g->n_sensors, kSensorsPerFwdBlock);
+      op.kseg = std::max(1, std::min<int32_t>(g->n_samples, kBlock));
+      op.nseg = g->n_samples > 0 ? ceil_div(g->n_samples, op.kseg) : 0;
+      const size_t rows = (size_t)op.n_atiles * (size_t)g->n_sensors * (size_t)op.wpa * 4;
+      const size_t tab = (size_t)op.n_atiles * (size_t)g->n_sensors * 4;
+      pl.part_rows_off = 0;
+      pl.klo_tab_off = align_up(rows, 256);
+      const size_t scr = align_up(pl.klo_tab_off + tab, 256);
+      const bool empty = P == 0 || M == 0;
+      if (!empty && scr <= ((size_t)1 << 40)) {
+        pl.fwd_scratch = scr;
+        pl.fp2_grid = op.n_atiles * op.n_chunks;
+        pl.gather_grid = g->n_sensors * op.nseg;
+        pl.two_pass = tuned.fwd_mode == 3;
+      }
+    }
   }
 
   op.out_scale = (float)(2.0 * inv_cdt);   // FP32 phase accumulates w / 2
@@ -261,7 +319,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
 CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   CglsLayout L{};
   const size_t A = 256;
-  L.g_q = std::max(plan.fp_grid, 1);
+  L.g_q = std::max(plan.two_pass ? plan.gather_grid : plan.fp_grid, 1);
   L.g_m = blas_grid(plan.M);
   L.g_p = blas_grid(plan.P);
   L.g_bp = std::max(plan.op.n_tiles, 1);
@@ -278,6 +336,7 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
   L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.vec_p = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.fwd = off; off = align_up(off + (plan.two_pass ? plan.fwd_scratch : 0), A);
   L.total = off;
   return L;
 }
@@ -301,6 +360,7 @@ LwLayout lw_layout(const Plan& plan) {
   L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
   L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.vec_v = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.fwd = off; off = align_up(off + (plan.two_pass ? plan.fwd_scratch : 0), A);
   L.total = off;
   return L;
 }
@@ -331,12 +391,24 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
   // A batched launch gives every work-group the largest LDS any frame needs,
   // so with use_tuning a frame keeps its tuned tiling only if that stays
   // within what the planner's rules give for the batch.
+  // The rule plans of a batch also keep the forward's LDS within
+  // kLdsBatchFwd (three work-groups per CU): a batched launch mixes frames of
+  // very different cost, and more resident work-groups hide the long ones.
   std::vector<Plan> rule(n_frames);
   size_t rule_bp = 0, rule_fp = 0;
-  const Tuning by_rule{0, 0, 0};
+  const Tuning by_rule{0, 0, 0, {0, 0, 0}};
+  int32_t segs[8];
+  const int nseg = fwd_seg_candidates(segs, 8);
   for (int i = 0; i < n_frames; ++i) {
     std::string m;
     pa_status st = make_plan(&frames[i], dtype, &rule[i], &m, &by_rule);
+    for (int c = nseg - 1; st == PA_OK && rule[i].fp_lds > kLdsBatchFwd && c >= 0; --c) {
+      if (segs[c] >= rule[i].op.fseg) continue;
+      Plan shorter;
+      const Tuning t{segs[c], 0, 0, {0, 0, 0}};
+      if (make_plan(&frames[i], dtype, &shorter, &m, &t) == PA_OK && shorter.op.fseg == segs[c])
+        rule[i] = shorter;
+    }
     if (st != PA_OK) {
       if (msg) *msg = "frame " + std::to_string(i) + ": " + m;
       return st;
@@ -355,6 +427,7 @@ pa_status make_batch_plan(const pa_geometry* frames, int32_t n_frames, pa_dtype 
     else
       B.plans[i] = rule[i];
   }
+  for (Plan& pl : B.plans) pl.two_pass = false;   // batched launches use the sensor-major forward
   B.tuned = use_tuning;
   B.ffix = B.plans[0].op.ffix != 0;   // one forward kernel per launch: every frame plans the same mode
   B.ndim = frames[0].ndim;

@@ -31,6 +31,9 @@ constexpr int kBlock = 256;          // lanes per work-group, every kernel
 constexpr size_t kLdsPreferred = 64 * 1024 - 256;  // dynamic LDS that keeps several work-groups per CU
 constexpr size_t kLdsMax = 160 * 1024 - 1024;      // gfx950: 160 KiB of LDS per work-group, minus static use
 constexpr int kFwdList = kBlock;     // forward operator: base tiles listed per round (one per lane)
+constexpr int kSensorsPerFwdBlock = 64;          // partial-row forward: one sensor per lane of a wave
+constexpr size_t kLdsPreferredFwd = 80 * 1024;   // partial-row forward pass 1: two work-groups per CU
+constexpr size_t kLdsBatchFwd = 48 * 1024;       // batched sensor-major forward: three work-groups per CU
 
 // Arithmetic of a dtype: the type of every vector element (images, traces,
 // CGLS vectors) and of the per-pair delay and weight.
@@ -60,6 +63,16 @@ struct OpParams {
   int32_t fnseg;            // forward: segments per trace (work-groups per sensor)
   int32_t fbins;            // forward: histogram bins per wave, fseg + 2 wp + 2
   int32_t ffix;             // forward, FP32 delay arithmetic: 1 = fixed-point tile rows, 0 = FP64 bins
+  // forward through partial rows (PA_F32 with a workspace): pass 1 scatters
+  // one forward tile for 64 sensors into LDS rows, pass 2 adds the rows up
+  int32_t msub[3];          // base tiles per forward tile, per axis
+  int32_t nsub;             // product
+  int32_t natile[3];        // forward tiles per axis
+  int32_t n_atiles;
+  int32_t n_chunks;         // sensor chunks of 64
+  int32_t wpa;              // LDS row stride of one sensor over a forward tile
+  int32_t kseg;             // pass 2: samples per work-group (<= 256, one per lane)
+  int32_t nseg;             // pass 2: segments per trace
   double near_r2;           // squared tile-centre distance (sample units) below which a
                             // sensor takes the FP64 delay path in the FP32-phase kernels
   float out_scale;          // converts accumulated kernel units to 1/metres (FP32 phase, float data)
@@ -84,20 +97,28 @@ PA_HD inline BpLayout bp_layout(int sc, int wp, size_t elem, size_t sc_bytes, si
   return L;
 }
 
-// Forward operator, per listed base tile: its index, the offset of its
+// Sensor-major forward operator, per listed base tile: the offset of its
 // window in the segment's histogram, near flag and the factor that turns the
 // tile's sum of |x| into a bound on any partial sum of its taps.
 struct FpTile {
-  int32_t tile;
   int32_t off;     // first bin of the tile's window in the FP64 histogram
   int32_t xoff;    // index in x of the tile's first pixel
-  int32_t lim;     // pixels of the tile inside the image per axis: nx | ny << 8 | nz << 16
+  int32_t lim;     // pixels of the tile inside the image per axis: nx | ny << 8 | nz << 16,
+                   // plus kFpNear when the sensor takes the FP64 delay path (FP32-phase kernels)
   float ib;        // 1 / (2 max(dmin, r_min)), dmin = distance from the sensor to the tile's box
-  int32_t near;    // 1: FP64 delay path (FP32-phase kernels)
-  int32_t pad[2];
+};
+constexpr int32_t kFpNear = 1 << 24;
+
+// The forward operator's per-(tile, sensor) delay constants with FP32 delay
+// arithmetic: the far-pair fields of the adjoint's constants (the same values
+// for the same tile and sensor).
+struct FpSC32 {
+  float E, DX2, DY2, DZ2, KRN, KR2N, KR2;
+  int32_t BASE;
 };
 
-constexpr int kFwdGroup = 4;  // forward: list entries a wave processes together (one fixed-point scale)
+constexpr int kFwdGroupMax = 8;  // forward: list entries a wave processes together (one fixed-point scale):
+                                 // 8 with float vectors, 4 with double
 
 // Forward operator LDS: a list of up to kFwdList base tiles with their
 // per-(tile, sensor) constants (sc_bytes each), one FP64 histogram of fbins
@@ -117,6 +138,25 @@ PA_HD inline FpLayout fp_layout(int fbins, int wp, size_t sc_bytes, bool fix) {
   return L;
 }
 
+// Partial-row forward operator, pass 1 LDS: 32-bit fixed-point rows of 64
+// sensors, the pixel offsets of a base tile, the forward tile's x values, the
+// rows' window starts and the per-sensor scales.
+struct Fp2Layout {
+  size_t hist, pixtab, xs, klo, inv, total;
+};
+PA_HD inline Fp2Layout fp2_layout(int wpa, int nsub) {
+  Fp2Layout L;
+  L.hist = 0;
+  // pixtab and xs each have four entries of slack: the scatter loop reads
+  // four pixels ahead without a bounds test
+  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * 4);
+  L.xs = L.pixtab + (size_t)(kBlock + 4) * 16;
+  L.klo = L.xs + align16(((size_t)nsub * kBlock + 4) * 4);
+  L.inv = L.klo + align16(kSensorsPerFwdBlock * 4);
+  L.total = L.inv + (kSensorsPerFwdBlock + 4 * (size_t)nsub) * sizeof(double);
+  return L;
+}
+
 struct Plan {
   OpParams op;
   int ndim;
@@ -125,6 +165,12 @@ struct Plan {
   int64_t P, M;             // pixels, samples (S*K)
   size_t bp_lds, fp_lds;    // dynamic LDS bytes
   int bp_grid, fp_grid;     // adjoint: one work-group per base tile; forward: one per (sensor, segment)
+  // partial-row forward (PA_F32): used where a workspace is given and two_pass is set
+  bool two_pass;
+  size_t fp2_lds;
+  int fp2_grid, gather_grid;
+  size_t fwd_scratch;       // workspace bytes for the partial rows and their window starts (0: not used)
+  size_t part_rows_off, klo_tab_off;
 };
 
 // Tiling choices an autotuning run can fix for a geometry shape.  Zero
@@ -132,7 +178,9 @@ struct Plan {
 struct Tuning {
   int32_t fwd_seg;       // forward operator: samples of a trace per work-group
   int32_t adj_lds;       // adjoint: LDS budget per work-group (bytes) that sets the sensor chunk
-  int32_t fwd_mode;      // forward, FP32 delay arithmetic: 1 = fixed-point tile rows, 2 = FP64 bins
+  int32_t fwd_mode;      // forward, FP32 delay arithmetic: 1 = fixed-point tile rows, 2 = FP64 bins,
+                         // 3 = partial rows (PA_F32 with a workspace)
+  int32_t fwd_tile[3];   // partial-row forward: base tiles per forward tile, per axis
 };
 
 // Fills *plan from g.  Returns PA_OK or an error with *msg set.  Never touches
@@ -151,6 +199,7 @@ void tune_clear();
 uint64_t tune_epoch();
 // Candidate tilings the autotuner times.
 int fwd_seg_candidates(int32_t* out, int max);
+int fwd_tile_candidates(int ndim, int (*out)[3], int max);
 int adj_lds_candidates(size_t* out, int max);
 
 // One frame of a batch as the batched kernels see it (device table, sorted
@@ -209,14 +258,14 @@ int blas_grid(int64_t n);
 
 // CGLS workspace layout.
 struct CglsLayout {
-  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, total;
+  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, fwd, total;
   int g_q, g_m, g_p, g_bp;  // partial counts: forward work-groups, over S*K, over pixels, adjoint tiles
 };
 CglsLayout cgls_layout(const Plan& plan, int32_t iters);
 
 // Landweber workspace layout.
 struct LwLayout {
-  size_t status, alpha0, sigma2, omega, part_r, part_s, part_x, part_n, vec_r, vec_q, vec_s, vec_v, total;
+  size_t status, alpha0, sigma2, omega, part_r, part_s, part_x, part_n, vec_r, vec_q, vec_s, vec_v, fwd, total;
   int g_m, g_p, g_bp;
 };
 LwLayout lw_layout(const Plan& plan);

@@ -149,10 +149,22 @@ def forward(x: torch.Tensor, geom, out: torch.Tensor | None = None, precision: s
         return out
     lib = _lib.load()
     cg = g.c_struct()
+    code = _code(x, precision)
+    ws = _forward_workspace(lib, cg, code, x.device)
     for xb, yb in zip(xs, ys):
-        _lib.check(lib.pa_forward(ctypes.byref(cg), _code(x, precision), xb.data_ptr() or None,
-                                  yb.data_ptr() or None, _stream(x.device)))
+        _lib.check(lib.pa_forward_ws(ctypes.byref(cg), code, xb.data_ptr() or None, yb.data_ptr() or None,
+                                     ws.data_ptr() if ws is not None else None, ws.numel() if ws is not None else 0,
+                                     _stream(x.device)))
     return out
+
+
+def _forward_workspace(lib, cg, code, device):
+    """A torch-owned workspace for pa_forward_ws (None when the plan needs none)."""
+    n = int(lib.pa_forward_workspace_bytes(ctypes.byref(cg), code))
+    if n == 0:
+        _lib.check(lib.pa_validate_geometry(ctypes.byref(cg), code))
+        return None
+    return torch.empty(n, dtype=torch.uint8, device=device)
 
 
 def adjoint(y: torch.Tensor, geom, out: torch.Tensor | None = None, precision: str | None = None) -> torch.Tensor:
@@ -196,8 +208,20 @@ class Operator:
         self._ref = ctypes.byref(self._cg)
         self._lib = _lib.load()
         _lib.check(self._lib.pa_validate_geometry(self._ref, self._code))
+        self._ws = None
 
     def forward_(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        n = int(self._lib.pa_forward_workspace_bytes(self._ref, self._code))   # follows later tunings
+        if n > (0 if self._ws is None else self._ws.numel()):
+            self._ws = torch.empty(n, dtype=torch.uint8, device=self.geom.device)
+        ws = self._ws
+        _lib.check(self._lib.pa_forward_ws(self._ref, self._code, x.data_ptr() or None, y.data_ptr() or None,
+                                           ws.data_ptr() if (n and ws is not None) else None, n,
+                                           torch.cuda.current_stream(x.device).cuda_stream))
+        return y
+
+    def forward_no_workspace_(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        """y := A x through pa_forward (the sensor-major method, no workspace)."""
         _lib.check(self._lib.pa_forward(self._ref, self._code, x.data_ptr() or None, y.data_ptr() or None,
                                         torch.cuda.current_stream(x.device).cuda_stream))
         return y
@@ -423,11 +447,30 @@ def autotune(geom, dtype: torch.dtype = torch.float32, device=None, precision: s
     y = torch.zeros(g.data_shape, dtype=dtype, device=g.device)
     t = _lib.PaTuning()
     lib = _lib.load()
-    _lib.check(lib.pa_autotune(ctypes.byref(g.c_struct()), _code(x, precision), x.data_ptr() or None,
-                               y.data_ptr() or None,
-                               _stream(g.device), ctypes.byref(t)))
-    return {"fwd_seg": int(t.fwd_seg), "fwd_mode": int(t.fwd_mode), "adj_lds_bytes": int(t.adj_lds_bytes),
+    cg = g.c_struct()
+    code = _code(x, precision)
+    n = int(lib.pa_autotune_workspace_bytes(ctypes.byref(cg), code))
+    ws = torch.empty(n, dtype=torch.uint8, device=g.device) if n else None
+    _lib.check(lib.pa_autotune(ctypes.byref(cg), code, x.data_ptr() or None, y.data_ptr() or None,
+                               ws.data_ptr() if ws is not None else None, n, _stream(g.device), ctypes.byref(t)))
+    return {"fwd_seg": int(t.fwd_seg), "fwd_mode": int(t.fwd_mode), "fwd_tile": tuple(int(v) for v in t.fwd_tile),
+            "adj_lds_bytes": int(t.adj_lds_bytes),
             "fwd_us": float(t.fwd_us), "adj_us": float(t.adj_us)}
+
+
+def tuning_set(geom, tuning: dict, dtype: torch.dtype = torch.float32, device=None,
+               precision: str | None = None) -> None:
+    """Records a tuning for this geometry's shape (e.g. a dict autotune returned
+    in an earlier process); missing keys keep the planner's rule."""
+    g = as_device_geometry(geom, device)
+    t = _lib.PaTuning()
+    t.fwd_seg = int(tuning.get("fwd_seg", 0))
+    t.fwd_mode = int(tuning.get("fwd_mode", 0))
+    for a, v in enumerate(tuning.get("fwd_tile", (0, 0, 0))):
+        t.fwd_tile[a] = int(v)
+    t.adj_lds_bytes = int(tuning.get("adj_lds_bytes", 0))
+    cg = g.c_struct()
+    _lib.check(_lib.load().pa_tuning_set(ctypes.byref(cg), dtype_code(dtype, precision), ctypes.byref(t)))
 
 
 def tuning_clear() -> None:

@@ -179,13 +179,36 @@ def test_batch_rejects_bad_frames_on_host(lib):
 
 def test_autotune_argument_checks_on_host(lib):
     vp = ctypes.c_void_p
-    lib.pa_autotune.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, vp, vp, vp, vp]
+    lib.pa_autotune.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp, vp]
+    lib.pa_autotune_workspace_bytes.argtypes = [ctypes.POINTER(Geom), ctypes.c_int]
+    lib.pa_autotune_workspace_bytes.restype = ctypes.c_size_t
     g = good()
-    assert lib.pa_autotune(ctypes.byref(g), 0, None, 1 << 20, None, None) == 1
-    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, (1 << 20) + 64, None, None) == 1
+    # FP32: the partial-row candidates need a workspace; FP64 times the sensor-major method only
+    assert lib.pa_autotune_workspace_bytes(ctypes.byref(g), 0) > 0
+    assert lib.pa_autotune_workspace_bytes(ctypes.byref(g), 1) == 0
+    assert lib.pa_autotune(ctypes.byref(g), 0, None, 1 << 20, None, 0, None, None) == 1
+    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, (1 << 20) + 64, None, 0, None, None) == 1
+    # a misaligned workspace and one that overlaps x
+    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, 1 << 28, (1 << 30) + 8, 4096, None, None) == 3
+    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, 1 << 28, 1 << 20, 4096, None, None) == 1
     g.dt = -1.0
-    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, 1 << 28, None, None) == 1
+    assert lib.pa_autotune(ctypes.byref(g), 0, 1 << 20, 1 << 28, None, 0, None, None) == 1
     assert lib.pa_tuning_clear() == 0
+
+
+def test_forward_workspace_checks_on_host(lib):
+    vp = ctypes.c_void_p
+    lib.pa_forward_workspace_bytes.argtypes = [ctypes.POINTER(Geom), ctypes.c_int]
+    lib.pa_forward_workspace_bytes.restype = ctypes.c_size_t
+    lib.pa_forward_ws.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
+    g = good()
+    # by rule the forward operator is the sensor-major one, which needs no workspace
+    assert lib.pa_forward_workspace_bytes(ctypes.byref(g), 0) == 0
+    assert lib.pa_forward_workspace_bytes(ctypes.byref(g), 2) == 0
+    assert lib.pa_forward_ws(ctypes.byref(g), 0, None, 1 << 20, None, 0, None) == 1
+    assert lib.pa_forward_ws(ctypes.byref(g), 0, 1 << 20, (1 << 20) + 64, None, 0, None) == 1
+    g.dt = -1.0
+    assert lib.pa_forward_workspace_bytes(ctypes.byref(g), 0) == 0
 
 
 def test_landweber_argument_checks_on_host(lib):
@@ -302,3 +325,31 @@ def test_freq_argument_checks_on_host(lib):
         assert fn(ctypes.byref(g), 0, 1e5, 1e5, 256, 1 << 20, 1 << 24, None, w, None) == 3
         assert fn(ctypes.byref(g), 0, 1e5, 1e5, 256, 1 << 20, 1 << 24, 1 << 30, w - 8, None) == 3
         assert fn(ctypes.byref(g), 0, 1e5, 1e5, 256, 1 << 20, (1 << 20) + 64, 1 << 30, w, None) == 1   # x, Y overlap
+
+
+def test_tuning_set_checks_on_host(lib):
+    from paper_2404_10928_amd._lib import PaTuning
+    lib.pa_tuning_set.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, ctypes.POINTER(PaTuning)]
+    lib.pa_forward_workspace_bytes.argtypes = [ctypes.POINTER(Geom), ctypes.c_int]
+    lib.pa_forward_workspace_bytes.restype = ctypes.c_size_t
+    g = good()
+    t = PaTuning()
+    try:
+        assert lib.pa_tuning_set(ctypes.byref(g), 0, None) == 1
+        t.fwd_mode = 4
+        assert lib.pa_tuning_set(ctypes.byref(g), 0, ctypes.byref(t)) == 1
+        t.fwd_mode = 3                       # partial rows need a tile
+        assert lib.pa_tuning_set(ctypes.byref(g), 0, ctypes.byref(t)) == 1
+        t.fwd_tile[0], t.fwd_tile[1], t.fwd_tile[2] = 2, 2, 1
+        assert lib.pa_tuning_set(ctypes.byref(g), 1, ctypes.byref(t)) == 2   # PA_F32 only
+        assert lib.pa_forward_workspace_bytes(ctypes.byref(g), 0) == 0
+        assert lib.pa_tuning_set(ctypes.byref(g), 0, ctypes.byref(t)) == 0
+        # now the partial-row forward is planned, and it needs a workspace
+        n = lib.pa_forward_workspace_bytes(ctypes.byref(g), 0)
+        assert n >= 64 * 48 * 4
+        t.fwd_tile[2] = 2                    # a 2D geometry has one tile along z
+        assert lib.pa_tuning_set(ctypes.byref(g), 0, ctypes.byref(t)) == 2
+        assert lib.pa_forward_workspace_bytes(ctypes.byref(g), 0) == n       # unchanged after a refusal
+    finally:
+        assert lib.pa_tuning_clear() == 0
+    assert lib.pa_forward_workspace_bytes(ctypes.byref(g), 0) == 0

@@ -21,6 +21,7 @@ import pytest
 
 import oracle
 from gpu_common import rel_l2, ring_geom, rounded
+from solve_band import gates
 from synth import add_noise, make_config
 
 pytestmark = pytest.mark.gpu
@@ -117,11 +118,17 @@ def test_c1_f32_history(pa):
     assert np.all(h[1:, 2] <= h[:-1, 2] * (1 + 1e-6))
 
 
-def test_c2_f32_solve(pa):
+@pytest.fixture(scope="module")
+def c2_ref():
     w = make_config("C2")
     g, y = problem(w)
     y32, y64 = rounded(y, np.float32)
     x_ref, h_ref, _ = oracle.cgls(g, y64, w.iters, w.lam)
+    return w, g, y32, y64, x_ref, h_ref
+
+
+def test_c2_f32_solve(pa, c2_ref):
+    w, g, y32, y64, x_ref, h_ref = c2_ref
     x, h, stop = gpu_cgls(pa, g, y32, w.iters, w.lam, np.float32)
     err = rel_hist(h, h_ref)
     e_x = rel_l2(x, x_ref)
@@ -132,6 +139,48 @@ def test_c2_f32_solve(pa):
     assert e_x <= 1e-4 and err[-1, 2] <= 1e-4 and err[-1, 0] <= 1e-4
     assert off_curve(h[:, 2], h_ref[:, 2]) == [] and off_curve(h[:, 0], h_ref[:, 0]) == []
 
+
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+def test_c2_fp64_vector_solves(pa, c2_ref, precision):
+    """PA_MIXED (FP64 vectors and sums around the FP32-arithmetic operator)
+    and PA_F64 on the 512x512 workload, from the same FP32-rounded data: the
+    iterate after 50 iterations within 1e-4 of the oracle's; PA_F64's whole
+    history within 1e-6 (a 6e-8 change of y moves the oracle's own history by
+    < 3e-9 here); PA_MIXED's history within 1e-4 or on the descent curve."""
+    w, g, y32, y64, x_ref, h_ref = c2_ref
+    yt = torch.from_numpy(y64).to("cuda")
+    x, h, stop = pa.cgls(yt, g, w.iters, w.lam, precision=None if precision == "f64" else "mixed")
+    x, h = x.cpu().numpy(), h.cpu().numpy()
+    err = rel_hist(h, h_ref)
+    e_x = rel_l2(x, x_ref)
+    print(f"C2 {precision}: iterate rel-L2 {e_x:.2e}; final F {err[-1, 2]:.2e} ||r|| {err[-1, 0]:.2e}; "
+          f"max over k: F {err[:, 2].max():.2e} ||r|| {err[:, 0].max():.2e}")
+    assert stop == -1
+    assert e_x <= 1e-4 and err[-1, 2] <= 1e-4 and err[-1, 0] <= 1e-4
+    if precision == "f64":
+        assert err[:, 0].max() <= 1e-6 and err[:, 2].max() <= 1e-6
+    else:
+        assert off_curve(h[:, 2], h_ref[:, 2]) == [] and off_curve(h[:, 0], h_ref[:, 0]) == []
+
+
+def test_c1_mixed_iterate(pa):
+    """The 128x128 workload with FP64 vectors around the FP32-arithmetic
+    operator: the history on the stable prefix, and the iterate and F after
+    20 iterations within 1e-4 of the oracle's, or within three times the band
+    the oracle's own solve spans when each application is perturbed by 1e-6
+    (the FP32 delays' rounding), which is wider here: 1.0e-2 on the iterate,
+    2.9e-3 on F (tests/solve_band.py)."""
+    w = make_config("C1")
+    g, y = problem(w)
+    x_ref, h_ref, _ = oracle.cgls(g, y, w.iters, w.lam)
+    x, h, stop = pa.cgls(torch.from_numpy(y).to("cuda"), g, w.iters, w.lam, precision="mixed")
+    e = rel_l2(x.cpu().numpy(), x_ref)
+    err = rel_hist(h.cpu().numpy(), h_ref)
+    gt = gates("c1", "mixed")
+    print(f"C1 mixed: iterate {e:.2e} (gate {gt['x']:.1e}); history k<={C1_F32_STABLE_K} "
+          f"F {err[:C1_F32_STABLE_K + 1, 2].max():.2e}; final F {err[-1, 2]:.2e} (gate {gt['F']:.1e})")
+    assert stop == -1 and e <= gt["x"] and err[-1, 2] <= gt["F"]
+    assert err[: C1_F32_STABLE_K + 1, 2].max() <= 1e-4
 
 
 def test_c2_under_autotuned_plans(pa):

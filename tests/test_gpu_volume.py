@@ -1,22 +1,24 @@
 """3D and precision modes: the 128^3-voxel, 1024-sensor hemisphere solve in
-PA_F32 (FP32 bulk, FP64 reductions) and PA_F64, 30 CGLS iterations each,
-against the FP64 oracle's solve stored in tests/golden/c5_cgls_reference.json
-(written by tests/golden/make_c5_reference.py, which calls only the oracle).
+PA_F32 (FP32 vectors, FP64 reductions), PA_MIXED (FP64 vectors around the
+FP32-arithmetic operator) and PA_F64, 30 CGLS iterations each, against the
+FP64 oracle's solve stored in tests/golden/c5_cgls_reference.json (written by
+tests/golden/make_c5_reference.py, which calls only the oracle).
 
-This solve is chaotic: a 1e-12 relative change of y moves the oracle's own
-F(x_k) by < 1e-13 up to k = 7, then by 8e-13, 2e-10, 1e-8, 4e-6 and 1.3e-3 at
-k = 8..12 (each further step amplifies by 1e2-1e3; larger perturbations
-reach that regime sooner).  Past that point any change of summation order
-gives another, equally valid, iterate, and no solve can match the oracle's
-x_30 to 1e-4.  The gates are therefore:
-  * the history on the stable prefix: PA_F64 within 1e-6 up to k = 9 (it
-    departs by 2e-11, 5e-9, 3e-7, 9e-5 at k = 8..11); PA_F32 within 1e-4 up
-    to k = 5 (3e-9 at k = 4, 2e-7 at 5, then 3e-5, 1e-2);
+This solve is chaotic.  A GPU solve rounds differently from the oracle in
+every operator application, and CG turns such differences into changes of
+the final F and iterate far above the rounding: the oracle's own solve, with
+every application perturbed by a relative 1e-13 (PA_F64-sized rounding),
+lands up to ~1e-2 away from itself (tests/golden/solve_spread.json, written
+by tests/golden/make_solve_spread.py, which calls only the oracle).  Past
+the stable prefix any of those trajectories is equally valid.  The gates:
+  * the history on the stable prefix: PA_F64 within 1e-6 up to k = 9;
+    PA_F32 and PA_MIXED within 1e-4 up to k = 5;
   * after the solve, the reported F_30 is the objective of the returned
-    iterate, evaluated by the oracle: ||A x_30 - y||^2 + lambda ||x_30||^2
-    within 1e-6 (PA_F64) / 1e-4 (PA_F32) of the history's last entry;
-  * F_30 within 5 % of the oracle's (the spread between valid solves, 1-3 %
-    here), and F non-increasing over the solve to 1e-6.
+    iterate, evaluated by the oracle (1e-6 PA_F64 and PA_MIXED, 1e-4 PA_F32);
+  * F_30 and the sampled x_30 within 1e-4 of the oracle's, or within three
+    times the band of the oracle's perturbed solves (PA_F64: the 1e-13 band;
+    PA_MIXED and PA_F32: the 1e-6 band of FP32 delays), tests/solve_band.py;
+  * F non-increasing over the solve to 1e-6.
 """
 import json
 import os
@@ -27,6 +29,7 @@ import pytest
 
 import oracle
 from gpu_common import rel_l2
+from solve_band import gates
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.join(HERE, "golden"))
@@ -35,8 +38,9 @@ from make_c5_reference import c5_data  # noqa: E402
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-STABLE_K = {"f64": 9, "f32": 5}
-HIST_TOL = {"f64": 1e-6, "f32": 1e-4}
+STABLE_K = {"f64": 9, "f32": 5, "mixed": 5}
+HIST_TOL = {"f64": 1e-6, "f32": 1e-4, "mixed": 1e-4}
+SELF_TOL = {"f64": 1e-6, "f32": 1e-4, "mixed": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -59,14 +63,15 @@ def reference():
 def solves(pa, reference):
     ref, w, g, y = reference
     out = {}
-    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+    for name, dt, prec in (("f32", torch.float32, None), ("f64", torch.float64, None),
+                           ("mixed", torch.float64, "mixed")):
         yt = torch.from_numpy(y).to("cuda", dtype=dt)
-        x, hist, stop = pa.cgls(yt, g, w.iters, w.lam)
+        x, hist, stop = pa.cgls(yt, g, w.iters, w.lam, precision=prec)
         out[name] = (x.double().cpu().numpy(), hist.cpu().numpy(), stop)
     return out
 
 
-@pytest.mark.parametrize("name", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["f64", "mixed", "f32"])
 def test_volume_solve(reference, solves, name):
     ref, w, g, y = reference
     x, hist, stop = solves[name]
@@ -78,15 +83,16 @@ def test_volume_solve(reference, solves, name):
     e_self = abs(hist[-1, 2] / F_true - 1)
     e_F = abs(hist[-1, 2] / h_ref[-1, 2] - 1)
     rise = np.max(hist[1:, 2] / hist[:-1, 2] - 1)
+    e_x = rel_l2(x.reshape(-1)[ref['sample_index']], np.array(ref['x_sample']))
+    gt = gates("c5", name)
     print(f"3D {name} per-k F error:", np.array2string(err[:, 2], precision=1))
     print(f"3D {name}: history k<={K}: F {err[:K + 1, 2].max():.2e} ||r|| {err[:K + 1, 0].max():.2e}; "
-          f"F_30 vs objective of x_30 {e_self:.2e}; F_30 vs oracle {e_F:.2e}; largest rise of F {rise:.1e}; "
-          f"iterate vs oracle (sampled) "
-          f"{rel_l2(x.reshape(-1)[ref['sample_index']], np.array(ref['x_sample'])):.2e}")
+          f"F_30 vs objective of x_30 {e_self:.2e}; F_30 vs oracle {e_F:.2e} (gate {gt['F']:.1e}); "
+          f"iterate vs oracle (sampled) {e_x:.2e} (gate {gt['x_sample']:.1e}); largest rise of F {rise:.1e}")
     assert stop == -1
     assert err[: K + 1, 2].max() <= HIST_TOL[name] and err[: K + 1, 0].max() <= HIST_TOL[name]
-    assert e_self <= (1e-6 if name == "f64" else 1e-4)
-    assert e_F <= 0.05
+    assert e_self <= SELF_TOL[name]
+    assert e_F <= gt["F"] and e_x <= gt["x_sample"]
     assert rise <= 1e-6
 
 
