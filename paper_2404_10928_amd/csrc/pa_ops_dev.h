@@ -296,6 +296,21 @@ __device__ __forceinline__ T lds_load(const T* addr) {
       static_cast<unsigned>(reinterpret_cast<size_t>(addr)));
 }
 
+// Non-finite test on a value's bits.  The operator kernels are built without
+// NaN semantics, so a floating-point test, or a bit test the compiler
+// recognises as one, may be folded away for a value it takes to be finite;
+// the empty asm makes the bits opaque, so the test stays an integer test.
+__device__ __forceinline__ bool non_finite_bits(float v) {
+  unsigned b = __float_as_uint(v);
+  asm volatile("" : "+v"(b));
+  return (b & 0x7f800000u) == 0x7f800000u;
+}
+__device__ __forceinline__ bool non_finite_bits(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  asm volatile("" : "+v"(b));
+  return (b & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
+}
+
 // floor(v + 0.5) as an int in one instruction (round half up; the two taps of
 // a pair are rounded the same way, so they still sum to the rounded total).
 __device__ __forceinline__ int round_i(float v) {
@@ -759,12 +774,17 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
           }
         }
         const float bound = wave_sum(sa) * (1.0f + 1.0f / 256.0f);
-        // (the kernels are built without NaN semantics, so non-finite values
-        // are recognised from their exponent bits)
-        if ((__float_as_uint(bound) & 0x7f800000u) == 0x7f800000u) {
+        // a NaN or infinite x (tested on the loaded values' bits), or a bound
+        // beyond float: the group's windows become NaN
+        bool nf = non_finite_bits(bound);
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) nf |= non_finite_bits(xv[u][q]);
+        if (__ballot(nf) != 0) {
           for (int e = rlo + lane; e < rhi; e += 64)   // stored as bits, out of reach of NaN folding
             reinterpret_cast<long long*>(hist)[e] = 0x7ff8000000000000ll;
-          continue;  // a NaN or infinite x (or a sum beyond float): the group's windows become NaN
+          continue;
         }
         if (bound == 0.0f) continue;  // all-zero tiles: nothing to add
         float b = bound;
@@ -934,6 +954,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   const bool s_ok = s < P.S;
 
   // pixel offsets of a base tile (same for every base tile) and the forward tile's x values
+  bool nfx = false;   // a NaN or infinite x among this lane's staged values
   {
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     make_pix<ND>(P, lx, ly, lz, pixtab[tid]);
@@ -944,6 +965,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
       const int ix = bx * TX + lx, iy = by * TY + ly, iz = bz * TZ + lz;
       T v = 0;
       if (ix < P.nx && iy < P.ny && iz < P.nz) v = x[((size_t)iz * P.ny + iy) * P.nx + ix];
+      nfx |= non_finite_bits(v);
       xs[m * kBlock + tid] = v;
     }
   }
@@ -979,7 +1001,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
       if (lane == 0) sa_m[m * 4 + wave] = v;
     }
-    __syncthreads();
+    const bool tile_nf = __syncthreads_or(nfx) != 0;   // (also the barrier for sa_m)
     // Tiny x (the forward tile's sum below ~1e-18): scale the staged values
     // by an exact power of two, so 2^30 / B_s stays finite and the fixed
     // point keeps its full range; the rows are scaled back on the way out.
@@ -987,7 +1009,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     double tsum = 0.0;
     for (int m = 0; m < 4 * P.nsub; ++m) tsum += sa_m[m];
     double post = 1.0, pre = 1.0;
-    if (tsum > 0.0 && tsum < 0x1p-60) {
+    if (!tile_nf && tsum > 0.0 && tsum < 0x1p-60) {
       const int e = min(120, -ilogb(tsum));
       const float sx = ldexpf(1.0f, e);
       for (int i = tid; i < P.nsub * kBlock; i += kBlock) xs[i] *= sx;
@@ -1016,10 +1038,9 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
       bound += sa * (0.5 / fmax(sqrt(d2), P.rmin));
     }
     bound *= 1.0 + 1.0 / 1024.0;
-    // A NaN or infinite x makes the bound non-finite (recognised from its
-    // exponent bits: the kernels are built without NaN semantics); the row
-    // then gets a NaN scale, so its traces come out NaN instead of zero.
-    const bool bad = (__double_as_longlong(bound) & 0x7ff0000000000000ll) == 0x7ff0000000000000ll;
+    // A NaN or infinite x in the forward tile (or a bound beyond double)
+    // gives the rows a NaN scale, so their traces come out NaN, not zero.
+    const bool bad = tile_nf || non_finite_bits(bound);
     if (!bad && bound > 0.0 && bound < 1e300) scl = (float)(1073741824.0 / bound);
     if (wave == 0) {
       // (selected as integer bits: under the no-NaN build flags a NaN operand
