@@ -104,6 +104,23 @@ size_t pa_forward_workspace_bytes(const pa_geometry* g, pa_dtype dtype);
 pa_status pa_forward_ws(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* workspace,
                         size_t workspace_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory or hand over a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): pa_forward_ws with the library's own device scratch in place of
+ * the caller's workspace.  The scratch is a static device array of
+ * PA_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends; its address on the current device is looked up on the first
+ * call there.  A shape whose planned forward needs more scratch than that
+ * (pa_forward_workspace_bytes) is refused with PA_ERR_UNSUPPORTED before
+ * anything is enqueued.  Nothing in the scratch has to start at zero: a call
+ * reads only bytes it wrote itself.  Every call on one GPU shares that GPU's
+ * one array, which keeps the last call's contents, so calls whose work
+ * overlaps on one GPU (other streams, other threads) race: serialise them.
+ * The current device must be the one x, y and hip_stream belong to.  Calls
+ * no hipMalloc, hipFree or other allocating routine. */
+#define PA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pa_status pa_forward_noalloc(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* hip_stream);
+
 /* x := A^T y, delay-and-interpolate back-projection: the exact adjoint of
  * pa_forward (the K^T products of Table 4). */
 pa_status pa_adjoint(const pa_geometry* g, pa_dtype dtype, const void* y, void* x, void* hip_stream);

@@ -30,7 +30,7 @@ PA_X0_ZERO = 1
 PA_USE_GRAPH = 2
 PA_NONNEG = 4
 
-EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_forward_workspace_bytes", "pa_forward_ws", "pa_adjoint",
+EXPORTS = ["pa_validate_geometry", "pa_forward", "pa_forward_workspace_bytes", "pa_forward_ws", "pa_forward_noalloc", "pa_adjoint",
            "pa_autotune_workspace_bytes", "pa_cgls_workspace_bytes", "pa_cgls_solve",
            "pa_cgls_stop_iteration", "pa_last_error", "pa_abi_version", "pa_batch_create", "pa_batch_destroy",
            "pa_batch_offsets", "pa_batch_workspace_bytes", "pa_batch_cgls_workspace_bytes", "pa_batch_forward",
@@ -79,6 +79,8 @@ def load(path: str = LIB_PATH):
     lib.pa_forward_workspace_bytes.restype = ctypes.c_size_t
     lib.pa_forward_ws.argtypes = [gp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
     lib.pa_forward_ws.restype = ctypes.c_int
+    lib.pa_forward_noalloc.argtypes = [gp, ctypes.c_int, vp, vp, vp]
+    lib.pa_forward_noalloc.restype = ctypes.c_int
     lib.pa_adjoint.argtypes = [gp, ctypes.c_int, vp, vp, vp]
     lib.pa_adjoint.restype = ctypes.c_int
     lib.pa_cgls_workspace_bytes.argtypes = [gp, ctypes.c_int, ctypes.c_int32]

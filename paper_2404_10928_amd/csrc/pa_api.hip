@@ -525,6 +525,54 @@ pa_status pa_forward(const pa_geometry* g, pa_dtype dtype, const void* x, void* 
   return PA_OK;
 }
 
+// The scratch of pa_forward_noalloc: a device array that every GPU the
+// library runs on holds until the process ends.  In host code `scratch`
+// names a host-side stand-in, not device memory: host code uses only the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[PA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kScratchDevices];   // per device: device address of `scratch`, looked up once
+
+pa_status noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices) return set_err(PA_ERR_UNSUPPORTED, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_err(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return set_err(PA_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return PA_OK;
+}
+}  // namespace
+
+pa_status pa_forward_noalloc(const pa_geometry* g, pa_dtype dtype, const void* x, void* y, void* hip_stream) {
+  g_err.clear();
+  pa::Plan pl;
+  pa_status st = plan_or_fail(g, dtype, &pl);
+  if (st != PA_OK) return st;
+  if ((st = check_vec(x, pl.P, pl.elem, "x")) != PA_OK) return st;
+  if ((st = check_vec(y, pl.M, pl.elem, "y")) != PA_OK) return st;
+  if (overlap(x, pl.P * pl.elem, y, pl.M * pl.elem)) return set_err(PA_ERR_INVALID_ARGUMENT, "x and y overlap");
+  const size_t need = pl.two_pass ? pl.fwd_scratch : 0;
+  if (need > PA_NOALLOC_SCRATCH_BYTES)
+    return set_err(PA_ERR_UNSUPPORTED, "the planned forward needs " + std::to_string(need) +
+                                           " bytes of scratch, above PA_NOALLOC_SCRATCH_BYTES (" +
+                                           std::to_string((size_t)PA_NOALLOC_SCRATCH_BYTES) + ")");
+  void* ws = nullptr;
+  if (need > 0 && (st = noalloc_scratch(&ws)) != PA_OK) return st;
+  PA_HIP(pa::launch_forward(pl, x, y, nullptr, ws, static_cast<hipStream_t>(hip_stream)), "forward kernels");
+  return PA_OK;
+}
+
 size_t pa_forward_workspace_bytes(const pa_geometry* g, pa_dtype dtype) {
   g_err.clear();
   pa::Plan pl;
