@@ -18,10 +18,23 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Sum of n partials, identical (same order) in every work-group that asks.
+// Loads per thread issued together before their adds (the partials are
+// L2 round trips; one at a time they dominate the small solver kernels).
+constexpr int kPartLoads = 8;
+
+// Sum of n partials, identical (same order) in every work-group that asks:
+// thread t adds part[t], part[t + 256], ... in increasing order, then the
+// block sum combines the threads.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, double* red) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) v += part[i];
+  for (int i0 = threadIdx.x; i0 < n; i0 += kPartLoads * kBlock) {
+    double t[kPartLoads];
+#pragma unroll
+    for (int u = 0; u < kPartLoads; ++u) t[u] = i0 + u * kBlock < n ? part[i0 + u * kBlock] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kPartLoads; ++u)
+      if (i0 + u * kBlock < n) v += t[u];
+  }
   return block_sum(v, red);
 }
 
@@ -39,10 +52,17 @@ __device__ __forceinline__ void sum_partials_n(const double* const (&part)[N], c
     v[j] = 0.0;
     nmax = n[j] > nmax ? n[j] : nmax;
   }
-  for (int i = threadIdx.x; i < nmax; i += kBlock) {
+  for (int i0 = threadIdx.x; i0 < nmax; i0 += kPartLoads * kBlock) {
+    double t[N][kPartLoads];
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-      if (i < n[j]) v[j] += part[j][i];
+    for (int u = 0; u < kPartLoads; ++u)
+#pragma unroll
+      for (int j = 0; j < N; ++j) t[j][u] = i0 + u * kBlock < n[j] ? part[j][i0 + u * kBlock] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kPartLoads; ++u)
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (i0 + u * kBlock < n[j]) v[j] += t[j][u];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
