@@ -38,10 +38,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 //   num = R^2 - kr^2 = (|D|^2 - kr^2) + 2 D.o + |o|^2
 // is formed in FP32 from small terms, and R - kr follows from one Newton step
 // on d (d + 2 kr) = num starting at the FP32 estimate R^2 * rsq(R^2) - kr.
-// The result is accurate to ~1e-6 samples.
+// The result is accurate to ~1e-6 samples.  The pixel enters through its
+// offset u in pixel pitches (o = hs u; half-integers, exact in FP32), so its
+// constants are the same for every plan: 2 D.o = u.(2 hs D) and
+// |o|^2 = hs^2 |u|^2.
 struct SC32 {
   float E;      // |D|^2 - kr^2
-  float DX2, DY2, DZ2;  // 2 D
+  float DXH, DYH, DZH;  // 2 hs D
   float KRN;    // -kr
   float KR2N;   // -2 kr
   float KR2;    // kr^2
@@ -69,8 +72,9 @@ template <typename T> struct SCOf;
 template <> struct SCOf<float> { using type = SC32; };
 template <> struct SCOf<double> { using type = SC64; };
 
-// Offsets of one pixel of a base tile from the tile centre, sample units.
-struct Pix32 { float ox, oy, oz, q; };
+// Offset of one pixel of a base tile from the tile centre: FP32, in pixel
+// pitches (ux, uy, uz) with uq = |u|^2; FP64, in sample units.
+struct Pix32 { float ux, uy, uz, uq; };
 struct Pix64 { double ox, oy, oz, pad; };
 template <typename T> struct PixOf;
 template <> struct PixOf<float> { using type = Pix32; };
@@ -84,13 +88,36 @@ __device__ __forceinline__ void pix_offsets(const OpParams& P, int lx, int ly, i
 }
 
 template <int ND>
-__device__ __forceinline__ void make_pix(const OpParams& P, int lx, int ly, int lz, Pix32& p) {
-  double o[3];
-  pix_offsets<ND>(P, lx, ly, lz, o);
-  p.ox = (float)o[0];
-  p.oy = (float)o[1];
-  p.oz = (float)o[2];
-  p.q = (float)(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+__host__ __device__ constexpr Pix32 unit_pix(int lx, int ly, int lz) {
+  const float ux = (float)lx - 0.5f * (Tile<ND>::X - 1);
+  const float uy = (float)ly - 0.5f * (Tile<ND>::Y - 1);
+  const float uz = ND == 3 ? (float)lz - 0.5f * (Tile<ND>::Z - 1) : 0.f;
+  return Pix32{ux, uy, uz, ux * ux + uy * uy + uz * uz};   // all exact
+}
+
+template <int ND>
+__device__ __forceinline__ void make_pix(const OpParams&, int lx, int ly, int lz, Pix32& p) {
+  p = unit_pix<ND>(lx, ly, lz);
+}
+
+// The unit offsets of a base tile's pixels in pixel order (lx fastest), in
+// constant memory: a wave-uniform index reads them with scalar loads.  Four
+// entries of slack past the tile: a loop may read four pixels ahead.
+struct PixTable {
+  Pix32 p[kBlock + 4];
+};
+template <int ND>
+constexpr PixTable make_pix_table() {
+  PixTable t{};
+  for (int i = 0; i < kBlock; ++i)
+    t.p[i] = unit_pix<ND>(i % Tile<ND>::X, (i / Tile<ND>::X) % Tile<ND>::Y, i / (Tile<ND>::X * Tile<ND>::Y));
+  return t;
+}
+__constant__ constexpr PixTable kPixTable2 = make_pix_table<2>();
+__constant__ constexpr PixTable kPixTable3 = make_pix_table<3>();
+template <int ND>
+__device__ __forceinline__ const Pix32* pix_table() {
+  return ND == 2 ? kPixTable2.p : kPixTable3.p;
 }
 
 template <int ND>
@@ -149,14 +176,14 @@ __device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], 
   double ra2 = dx * dx + dy * dy + dz * dz;
   double kr = rint(sqrt(ra2));
   if (!active) {  // benign constants: num = |o|^2 + 1 >= 1, a delay of at most |o| + 1, zero weight
-    c.E = 1.f; c.DX2 = 0.f; c.DY2 = 0.f; c.DZ2 = 0.f; c.KRN = 0.f; c.KR2N = 0.f; c.KR2 = 0.f;
+    c.E = 1.f; c.DXH = 0.f; c.DYH = 0.f; c.DZH = 0.f; c.KRN = 0.f; c.KR2N = 0.f; c.KR2 = 0.f;
     c.CMIN = 1.f; c.BASE = row_elems * esz; c.act = 0; c.HALF = 0.f;
     return;
   }
   c.E = (float)(ra2 - kr * kr);
-  c.DX2 = (float)(2.0 * dx);
-  c.DY2 = (float)(2.0 * dy);
-  c.DZ2 = (float)(2.0 * dz);
+  c.DXH = (float)(2.0 * P.hs * dx);
+  c.DYH = (float)(2.0 * P.hs * dy);
+  c.DZH = (float)(2.0 * P.hs * dz);
   c.KRN = (float)(-kr);
   c.KR2N = (float)(-2.0 * kr);
   c.KR2 = (float)(kr * kr);
@@ -198,12 +225,12 @@ static_assert(sizeof(Near32) == 32, "Near32 layout");
 // instruction is emitted: both choices give the same taps, and the kernels
 // use whichever schedules better (measured: A without, A^T with).
 template <int ND, bool FRAC, int ESZ, bool CLAMP, typename C>
-__device__ __forceinline__ void phase32(const C& c, float cmin, float half, const Pix32& px, float t0f, int& kbyte,
-                                        float& f, float& wt) {
-  float t = px.q + c.E;
-  float num = fmaf(px.oy, c.DY2, t);
-  if (ND == 3) num = fmaf(px.oz, c.DZ2, num);
-  num = fmaf(px.ox, c.DX2, num);
+__device__ __forceinline__ void phase32(const C& c, float cmin, float half, const Pix32& px, float t0f, float hs2,
+                                        int& kbyte, float& f, float& wt) {
+  float t = fmaf(px.uq, hs2, c.E);
+  float num = fmaf(px.uy, c.DYH, t);
+  if (ND == 3) num = fmaf(px.uz, c.DZH, num);
+  num = fmaf(px.ux, c.DXH, num);
   if (CLAMP) num = fmaxf(num, cmin);
   const float R2 = num + c.KR2;
   const float w = __builtin_amdgcn_rsqf(R2);
@@ -218,22 +245,24 @@ __device__ __forceinline__ void phase32(const C& c, float cmin, float half, cons
 }
 
 template <int ND, bool FRAC, int ESZ, bool CLAMP = true>
-__device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, int& kbyte, float& f, float& wt) {
-  phase32<ND, FRAC, ESZ, CLAMP>(c, c.CMIN, c.HALF, px, t0f, kbyte, f, wt);
+__device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, float hs2, int& kbyte, float& f,
+                                      float& wt) {
+  phase32<ND, FRAC, ESZ, CLAMP>(c, c.CMIN, c.HALF, px, t0f, hs2, kbyte, f, wt);
 }
 
 // Forward operator: far pairs only (active, no clamp reached), weight 1 / (2R).
 template <int ND, bool FRAC, int ESZ, bool CLAMP = false>
-__device__ __forceinline__ void phase(const FpSC32& c, const Pix32& px, float t0f, int& kbyte, float& f, float& wt) {
-  phase32<ND, FRAC, ESZ, false>(c, 0.f, 0.5f, px, t0f, kbyte, f, wt);
+__device__ __forceinline__ void phase(const FpSC32& c, const Pix32& px, float t0f, float hs2, int& kbyte, float& f,
+                                      float& wt) {
+  phase32<ND, FRAC, ESZ, false>(c, 0.f, 0.5f, px, t0f, hs2, kbyte, f, wt);
 }
 
 __device__ __forceinline__ FpSC32 fp_sc(const SC32& c) {
   FpSC32 o;
   o.E = c.E;
-  o.DX2 = c.DX2;
-  o.DY2 = c.DY2;
-  o.DZ2 = c.DZ2;
+  o.DXH = c.DXH;
+  o.DYH = c.DYH;
+  o.DZH = c.DZH;
   o.KRN = c.KRN;
   o.KR2N = c.KR2N;
   o.KR2 = c.KR2;
@@ -264,7 +293,8 @@ __device__ __forceinline__ void phase_near(const Near32& n, const double o[3], d
 }
 
 template <int ND, bool FRAC, int ESZ, bool CLAMP = true>
-__device__ __forceinline__ void phase(const SC64& c, const Pix64& px, float, int& kbyte, double& f, double& wt) {
+__device__ __forceinline__ void phase(const SC64& c, const Pix64& px, float, float, int& kbyte, double& f,
+                                      double& wt) {
   const double dx = px.ox + c.DX;
   const double dy = px.oy + c.DY;
   double R2 = dx * dx + dy * dy;
@@ -481,7 +511,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
       PH f[4], wt[4];
       T y0[4], y1[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) phase<ND, FRAC, (int)sizeof(T)>(sct[j + u], px, t0f, kb[u], f[u], wt[u]);
+      for (int u = 0; u < 4; ++u) phase<ND, FRAC, (int)sizeof(T)>(sct[j + u], px, t0f, P.hs2f, kb[u], f[u], wt[u]);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb[u]));
@@ -494,7 +524,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
     for (; j < nfar; ++j) {
       int kb;
       PH f, wt;
-      phase<ND, FRAC, (int)sizeof(T)>(sct[j], px, t0f, kb, f, wt);
+      phase<ND, FRAC, (int)sizeof(T)>(sct[j], px, t0f, P.hs2f, kb, f, wt);
       const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
       const T y0 = lds_load(tap);
       const T y1 = lds_load(tap + 1);
@@ -817,7 +847,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
             int kb;
             PH f, wt;
             if constexpr (FIX) {
-              phase<ND, FRAC, HB, false>(c, px[q], t0f, kb, f, wt);
+              phase<ND, FRAC, HB, false>(c, px[q], t0f, P.hs2f, kb, f, wt);
               const float vs = (wt * (float)xv[u][q]) * scl;
               const int it = round_i(vs);
               const int i1 = round_i(vs * f);
@@ -825,7 +855,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
               lds_add(bin, it - i1);
               lds_add(bin + 1, i1);
             } else {
-              phase<ND, FRAC, HB, false>(c, px[q], t0f, kb, f, wt);
+              phase<ND, FRAC, HB, false>(c, px[q], t0f, P.hs2f, kb, f, wt);
               const double v = (double)wt * (double)xv[u][q];
               const double a1 = v * (double)f;
               double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
@@ -936,7 +966,6 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   using H = typename std::conditional<F32, int, double>::type;
   constexpr int HB = (int)sizeof(H);
   H* hist = reinterpret_cast<H*>(smem + L.hist);
-  PX* pixtab = reinterpret_cast<PX*>(smem + L.pixtab);
   T* xs = reinterpret_cast<T*>(smem + L.xs);
   int* klo_a = reinterpret_cast<int*>(smem + L.klo);
   double* inv_a = reinterpret_cast<double*>(smem + L.inv);
@@ -957,7 +986,6 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   bool nfx = false;   // a NaN or infinite x among this lane's staged values
   {
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    make_pix<ND>(P, lx, ly, lz, pixtab[tid]);
     for (int m = 0; m < P.nsub; ++m) {
       const int bx = ax * P.msub[0] + m % P.msub[0];
       const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
@@ -1080,35 +1108,35 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     const T* xm = xs + m * kBlock;
     // Every pixel of the base tile, in order, four per step.  Pixels beyond
     // the image edge have x = 0 (and taps inside the window), so they add
-    // zeros.  The next four pixels' constants are read before this step's
-    // LDS adds are issued, so the adds never hold up the reads (the last
-    // step reads four entries past the range, into the arrays' slack); two
-    // register sets alternate, and the pixel index lives in a VGPR so the
-    // reads take immediate offsets.
+    // zeros.  The pixel offsets come from the constant table by scalar loads
+    // and the four x values from one LDS read, issued for the next four
+    // pixels before this step's LDS adds (the last step reads four entries
+    // past the range, into the arrays' slack); two register sets alternate.
     constexpr int NPIX = TX * TY * TZ;
     static_assert(NPIX % 32 == 0, "eight pixels per loop trip and up to four parts");
     const int p_lo = part * (NPIX / parts);
     const int p_hi = p_lo + NPIX / parts;
-    int vo = p_lo;
-    asm volatile("" : "+v"(vo));
+    const PX* ptab = pix_table<ND>();
+    float hs2v = P.hs2f;
+    asm volatile("" : "+v"(hs2v));  // a VGPR operand: the pixel's uq is the FMA's one scalar operand
+    int po = p_lo;
     PX pa_[4], pb_[4];
-    T xa_[4], xb_[4];
-    auto load4 = [&](PX (&pp)[4], T (&xx)[4]) {
+    float4 xa_, xb_;
+    auto load4 = [&](PX (&pp)[4], float4& xx) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        pp[j] = pixtab[vo + j];
-        xx[j] = xm[vo + j];
-      }
-      vo += 4;
+      for (int j = 0; j < 4; ++j) pp[j] = ptab[po + j];
+      xx = *reinterpret_cast<const float4*>(xm + po);
+      po += 4;
     };
-    auto scatter4 = [&](const PX (&pp)[4], const T (&xx)[4]) {
+    auto scatter4 = [&](const PX (&pp)[4], const float4& xx) {
+      const float xv[4] = {xx.x, xx.y, xx.z, xx.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         int kb;
         T f, wt;
-        phase<ND, FRAC, HB, false>(c, pp[j], t0f, kb, f, wt);
+        phase<ND, FRAC, HB, false>(c, pp[j], t0f, hs2v, kb, f, wt);
         H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
-        const float vs = (wt * xx[j]) * scl;   // (wt = 1 / (2R) also corrects the delay: not pre-scaled)
+        const float vs = (wt * xv[j]) * scl;   // (wt = 1 / (2R) also corrects the delay: not pre-scaled)
         const int i1 = round_i(vs * f);
         lds_add(bin, round_i(vs) - i1);
         lds_add(bin + 1, i1);

@@ -155,6 +155,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   op.S = g->n_sensors;
   op.K = g->n_samples;
   op.hs = hs;
+  op.hs2f = (float)(hs * hs);
   op.inv_cdt = inv_cdt;
   op.rmin = (g->r_min > 0 ? g->r_min : 0.5 * g->h) * inv_cdt;
   const double t0i = std::floor(T0);

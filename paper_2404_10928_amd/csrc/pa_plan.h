@@ -48,6 +48,7 @@ struct OpParams {
   int32_t S, K;             // sensors, samples
   double org[3];            // position of pixel (0,0,0), sample units
   double hs;                // pixel pitch, sample units
+  float hs2f;               // hs^2 in FP32 (the FP32 phase's |o|^2 = hs^2 |u|^2 term)
   double rmin;              // distance clamp, sample units
   double inv_cdt;           // metres -> sample units
   int32_t t0i;              // floor(t0 / dt)
@@ -113,7 +114,7 @@ constexpr int32_t kFpNear = 1 << 24;
 // arithmetic: the far-pair fields of the adjoint's constants (the same values
 // for the same tile and sensor).
 struct FpSC32 {
-  float E, DX2, DY2, DZ2, KRN, KR2N, KR2;
+  float E, DXH, DYH, DZH, KRN, KR2N, KR2;
   int32_t BASE;
 };
 
@@ -142,15 +143,14 @@ PA_HD inline FpLayout fp_layout(int fbins, int wp, size_t sc_bytes, bool fix) {
 // sensors, the pixel offsets of a base tile, the forward tile's x values, the
 // rows' window starts and the per-sensor scales.
 struct Fp2Layout {
-  size_t hist, pixtab, xs, klo, inv, total;
+  size_t hist, xs, klo, inv, total;
 };
 PA_HD inline Fp2Layout fp2_layout(int wpa, int nsub) {
   Fp2Layout L;
   L.hist = 0;
-  // pixtab and xs each have four entries of slack: the scatter loop reads
-  // four pixels ahead without a bounds test
-  L.pixtab = align16((size_t)kSensorsPerFwdBlock * wpa * 4);
-  L.xs = L.pixtab + (size_t)(kBlock + 4) * 16;
+  // xs has four entries of slack: the scatter loop reads four pixels ahead
+  // without a bounds test
+  L.xs = align16((size_t)kSensorsPerFwdBlock * wpa * 4);
   L.klo = L.xs + align16(((size_t)nsub * kBlock + 4) * 4);
   L.inv = L.klo + align16(kSensorsPerFwdBlock * 4);
   L.total = L.inv + (kSensorsPerFwdBlock + 4 * (size_t)nsub) * sizeof(double);
