@@ -263,12 +263,12 @@ pa_status pa_freq_adjoint(const pa_geometry* g, pa_dtype dtype, double f0, doubl
  * gives (the frames one after another, in the order passed to
  * pa_batch_create).  The batched kernels run the single-frame device code on
  * each frame's own plan and form every partial sum in the same order, so a
- * frame gets its single-frame result bit for bit in PA_F32 (whose forward
- * operator sums integers) and, in PA_F64, to the rounding of the forward
- * operator's FP64 histogram adds, which run in hardware order in every call.
- * (A frame whose autotuned tiling would raise the LDS of the whole batched
- * launch above what the planner's rules give is planned by rule; it then
- * matches a single-frame call planned by rule.)
+ * frame's result is the same, bit for bit, as that frame batched on its own,
+ * and as a single-frame call under the same plan.  Batched launches use the
+ * sensor-major forward (no workspace).  Their planner keeps each frame's
+ * forward LDS within 48 KiB (shorter trace segments than a single-frame
+ * plan may take), and a frame whose autotuned tiling would raise the LDS of
+ * the whole launch above what those rules give is planned by rule.
  */
 typedef struct pa_batch pa_batch;
 

@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(kBlock) fp2_kernel(OpParams P, const float* __
 __global__ void __launch_bounds__(kBlock) fp_gather_kernel(OpParams P, const float* __restrict__ rows,
                                                             const int* __restrict__ klo_tab, float* __restrict__ y,
                                                             double* __restrict__ part_q) {
-  gather_body(P, blockIdx.x, blockIdx.x, rows, klo_tab, y, part_q);
+  gather_body(P, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, rows, klo_tab, y, part_q);
 }
 
 // ---------------------------------------------------------------------------

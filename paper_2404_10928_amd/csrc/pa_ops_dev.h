@@ -971,8 +971,11 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   double* inv_a = reinterpret_cast<double*>(smem + L.inv);
   __shared__ double red[4];
 
-  const int chunk = b % P.n_chunks;
-  const int at = b / P.n_chunks;
+  // chunk-major: with the XCD remap of the launch, each XCD takes a
+  // contiguous run of (chunk, tile) blocks, so one chunk's rows are written
+  // within two XCDs, where pass 2 (remapped the same way) reads them
+  const int chunk = b / P.n_atiles;
+  const int at = b - chunk * P.n_atiles;
   const int ax = at % P.natile[0];
   const int ay = (at / P.natile[0]) % P.natile[1];
   const int az = at / (P.natile[0] * P.natile[1]);
@@ -1207,8 +1210,11 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
 // window starts prefetched); then the work-group scales, writes y and forms
 // the FP64 partial of ||y||^2.  No atomics: the result is the same on every
 // run.  Rows and window starts are sensor-major, so one sensor's rows are
-// contiguous.
-constexpr int kGatherLoads = 16;
+// contiguous.  The launch remaps work-groups so each XCD takes a contiguous
+// run of sensors: at the 512x512 workload (four chunks of 64 sensors) those
+// are rows pass 1 wrote on the same pair of XCDs, half of them in this
+// XCD's own L2.
+constexpr int kGatherLoads = 8;
 
 __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx, const float* __restrict__ rows,
                                             const int* __restrict__ klo_tab, float* __restrict__ y,
