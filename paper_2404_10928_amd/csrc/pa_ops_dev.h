@@ -1000,58 +1000,44 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
       xs[m * kBlock + tid] = v;
     }
   }
-  // this lane's sensor and its window over the whole forward tile
+  // this lane's sensor
   double sp[3];
   sensor_pos<ND>(P, s_ok ? s : P.S - 1, sp);
-  bool in_trace;
-  int kl;
-  {
-    double lo[3], hi[3];
-    const int T3[3] = {TX, TY, TZ};
-    double r0[3];
-    tile_ref<ND>(P, ax * P.msub[0], ay * P.msub[1], az * P.msub[2], r0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
-      hi[a] = lo[a] + (P.msub[a] * T3[a] - 1) * P.hs;
-    }
-    if (ND == 2) { lo[2] = 0.0; hi[2] = 0.0; }
-    kl = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wpa);
-  }
-  const bool active = s_ok && in_trace;
   // Fixed-point scale: a tap of pixel p in base tile m is at most
   // |x_p| / (2 dmin_m), dmin_m being the distance from this lane's sensor to
   // base tile m (clamped at r_min), so B_s = sum_m (sum_{p in m} |x_p|) /
-  // (2 dmin_m) bounds every partial sum of the row.
-  float scl = 0.f;
-  if constexpr (F32) {
-    double* sa_m = reinterpret_cast<double*>(smem + L.inv) + NS;  // [nsub][4] per-wave partials
-    for (int m = 0; m < P.nsub; ++m) {
-      double v = fabs((double)xs[m * kBlock + tid]);
+  // (2 dmin_m) bounds every partial sum of the row.  The four waves hold the
+  // same 64 sensors, so the FP64 per-sensor work is split between them: wave
+  // w forms the terms of base tiles w, w + 4, ..., wave 0 the window over the
+  // forward tile, and wave 0 adds the terms in tile order.
+  double* sa_m = reinterpret_cast<double*>(smem + L.inv) + NS;  // [nsub][4] per-wave sums of |x|
+  double* bterm = sa_m + 4 * P.nsub;                              // [nsub][64] bound terms
+  float* scl_a = reinterpret_cast<float*>(bterm + P.nsub * NS);   // [64] fixed-point scales
+  for (int m = 0; m < P.nsub; ++m) {
+    double v = fabs((double)xs[m * kBlock + tid]);
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (lane == 0) sa_m[m * 4 + wave] = v;
-    }
-    const bool tile_nf = __syncthreads_or(nfx) != 0;   // (also the barrier for sa_m)
-    // Tiny x (the forward tile's sum below ~1e-18): scale the staged values
-    // by an exact power of two, so 2^30 / B_s stays finite and the fixed
-    // point keeps its full range; the rows are scaled back on the way out.
-    // (The sum is the same in every lane, so the branch is uniform.)
-    double tsum = 0.0;
-    for (int m = 0; m < 4 * P.nsub; ++m) tsum += sa_m[m];
-    double post = 1.0, pre = 1.0;
-    if (!tile_nf && tsum > 0.0 && tsum < 0x1p-60) {
-      const int e = min(120, -ilogb(tsum));
-      const float sx = ldexpf(1.0f, e);
-      for (int i = tid; i < P.nsub * kBlock; i += kBlock) xs[i] *= sx;
-      __syncthreads();
-      pre = (double)sx;
-      post = ldexp(1.0, -e);
-    }
-    double bound = 0.0;
-    for (int m = 0; m < P.nsub; ++m) {
-      const double sa = pre * ((sa_m[m * 4 + 0] + sa_m[m * 4 + 1]) + (sa_m[m * 4 + 2] + sa_m[m * 4 + 3]));
-      if (sa == 0.0) continue;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) sa_m[m * 4 + wave] = v;
+  }
+  const bool tile_nf = __syncthreads_or(nfx) != 0;   // (also the barrier for sa_m)
+  // Tiny x (the forward tile's sum below ~1e-18): scale the staged values
+  // by an exact power of two, so 2^30 / B_s stays finite and the fixed
+  // point keeps its full range; the rows are scaled back on the way out.
+  // (The sum is the same in every lane, so the branch is uniform.)
+  double tsum = 0.0;
+  for (int m = 0; m < 4 * P.nsub; ++m) tsum += sa_m[m];
+  double post = 1.0, pre = 1.0;
+  if (!tile_nf && tsum > 0.0 && tsum < 0x1p-60) {
+    const int e = min(120, -ilogb(tsum));
+    const float sx = ldexpf(1.0f, e);
+    for (int i = tid; i < P.nsub * kBlock; i += kBlock) xs[i] *= sx;
+    pre = (double)sx;
+    post = ldexp(1.0, -e);
+  }
+  for (int m = wave; m < P.nsub; m += 4) {
+    const double sa = pre * ((sa_m[m * 4 + 0] + sa_m[m * 4 + 1]) + (sa_m[m * 4 + 2] + sa_m[m * 4 + 3]));
+    double term = 0.0;
+    if (sa != 0.0) {
       const int bx = ax * P.msub[0] + m % P.msub[0];
       const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
       const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
@@ -1066,23 +1052,47 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
         const double e = fmax(fmax(lo[a] - sp[a], sp[a] - hi[a]), 0.0);
         d2 += e * e;
       }
-      bound += sa * (0.5 / fmax(sqrt(d2), P.rmin));
+      term = sa * (0.5 / fmax(sqrt(d2), P.rmin));
     }
+    bterm[m * NS + lane] = term;
+  }
+  if (wave == 0) {
+    // this lane's window over the whole forward tile
+    bool in_trace;
+    double lo[3], hi[3];
+    const int T3[3] = {TX, TY, TZ};
+    double r0[3];
+    tile_ref<ND>(P, ax * P.msub[0], ay * P.msub[1], az * P.msub[2], r0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = r0[a] - 0.5 * (T3[a] - 1) * P.hs;
+      hi[a] = lo[a] + (P.msub[a] * T3[a] - 1) * P.hs;
+    }
+    if (ND == 2) { lo[2] = 0.0; hi[2] = 0.0; }
+    const int kl0 = window_lo<ND>(P, lo, hi, sp, &in_trace, P.wpa);
+    klo_a[lane] = s_ok && in_trace ? kl0 : P.K + 8;
+  }
+  for (int e = tid; e < NS * P.wpa; e += kBlock) hist[e] = 0;
+  __syncthreads();
+  if (wave == 0) {
+    double bound = 0.0;
+    for (int m = 0; m < P.nsub; ++m) bound += bterm[m * NS + lane];
     bound *= 1.0 + 1.0 / 1024.0;
     // A NaN or infinite x in the forward tile (or a bound beyond double)
     // gives the rows a NaN scale, so their traces come out NaN, not zero.
     const bool bad = tile_nf || non_finite_bits(bound);
-    if (!bad && bound > 0.0 && bound < 1e300) scl = (float)(1073741824.0 / bound);
-    if (wave == 0) {
-      // (selected as integer bits: under the no-NaN build flags a NaN operand
-      // of a floating-point select may be folded away)
-      const long long v = __double_as_longlong(scl > 0.f ? post / (double)scl : 0.0);
-      reinterpret_cast<long long*>(inv_a)[lane] = bad ? 0x7ff8000000000000ll : v;
-    }
+    float sc = 0.f;
+    if (!bad && bound > 0.0 && bound < 1e300) sc = (float)(1073741824.0 / bound);
+    scl_a[lane] = sc;
+    // (selected as integer bits: under the no-NaN build flags a NaN operand
+    // of a floating-point select may be folded away)
+    const long long v = __double_as_longlong(sc > 0.f ? post / (double)sc : 0.0);
+    reinterpret_cast<long long*>(inv_a)[lane] = bad ? 0x7ff8000000000000ll : v;
   }
-  if (wave == 0) klo_a[lane] = active ? kl : P.K + 8;
-  for (int e = tid; e < NS * P.wpa; e += kBlock) hist[e] = 0;
   __syncthreads();
+  const float scl = scl_a[lane];
+  const int kl = klo_a[lane];
+  const bool active = kl != P.K + 8;
 
   const float t0f = P.t0f;
   // Work items: (base tile m, part).  With fewer than four base tiles per

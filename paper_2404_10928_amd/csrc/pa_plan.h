@@ -33,7 +33,8 @@ constexpr size_t kLdsMax = 160 * 1024 - 1024;      // gfx950: 160 KiB of LDS per
 constexpr int kFwdList = kBlock;     // forward operator: base tiles listed per round (one per lane)
 constexpr int kSensorsPerFwdBlock = 64;          // partial-row forward: one sensor per lane of a wave
 constexpr size_t kLdsPreferredFwd = 80 * 1024;   // partial-row forward pass 1: two work-groups per CU
-constexpr size_t kLdsBatchFwd = 48 * 1024;       // batched sensor-major forward: three work-groups per CU
+constexpr size_t kLdsBatchFwd = 47 * 1024;       // batched sensor-major forward: with its ~1 KiB of static LDS
+                                                  // at most 48 KiB, three work-groups per CU
 
 // Arithmetic of a dtype: the type of every vector element (images, traces,
 // CGLS vectors) and of the per-pair delay and weight.
@@ -153,7 +154,10 @@ PA_HD inline Fp2Layout fp2_layout(int wpa, int nsub) {
   L.xs = align16((size_t)kSensorsPerFwdBlock * wpa * 4);
   L.klo = L.xs + align16(((size_t)nsub * kBlock + 4) * 4);
   L.inv = L.klo + align16(kSensorsPerFwdBlock * 4);
-  L.total = L.inv + (kSensorsPerFwdBlock + 4 * (size_t)nsub) * sizeof(double);
+  // inv: row scales [64], per-wave sums of |x| [nsub][4], bound terms
+  // [nsub][64] (doubles), then the fixed-point scales [64] (floats)
+  L.total = L.inv + (kSensorsPerFwdBlock + 4 * (size_t)nsub + (size_t)nsub * kSensorsPerFwdBlock) * sizeof(double) +
+            kSensorsPerFwdBlock * sizeof(float);
   return L;
 }
 
