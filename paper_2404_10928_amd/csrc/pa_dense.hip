@@ -86,6 +86,7 @@ __device__ __forceinline__ double vdot(const f64x2& a, const f64x2& b) { return 
 
 constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerBlock = kRowsPerWave * (kThreads / 64);
+constexpr int64_t kSplitBelowBlocks = 2048;   // 16-row work-groups below which rows are split over waves
 
 // y = A x: each wave owns four rows and streams them in 16-byte vectors, so
 // one load of x feeds four rows.  FP64 accumulation, wave-shuffle reduction
@@ -125,6 +126,56 @@ __global__ void __launch_bounds__(kThreads) dense_gemv_kernel(const T* __restric
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0 && row0 + r < M) y[row0 + r] = (T)s;
+  }
+}
+
+// y = A x for matrices with few rows (fewer work-groups of the kernel above
+// than the chip has CUs to keep busy): the four waves of a work-group share
+// its four rows, wave w taking every fourth 64-vector stretch of columns, so
+// four times as many waves stream the matrix.  Each wave's FP64 sums are
+// reduced by shuffles, then the four waves' in wave order through LDS.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) dense_gemv_split_kernel(const T* __restrict__ a, const T* __restrict__ x,
+                                                                    T* __restrict__ y, int64_t M, int64_t P,
+                                                                    int64_t ld) {
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  __shared__ double red[4][kRowsPerWave];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsPerWave;
+  double acc[kRowsPerWave] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t nv = ld / VN;
+  for (int64_t v = (int64_t)wave * 64 + lane; v < nv; v += kThreads) {
+    const int64_t p = v * VN;
+    V xv;
+    if (p + VN <= P) {
+      xv = *reinterpret_cast<const V*>(x + p);
+    } else {
+      T t[VN];
+#pragma unroll
+      for (int j = 0; j < VN; ++j) t[j] = p + j < P ? x[p + j] : (T)0;
+      xv = *reinterpret_cast<const V*>(t);
+    }
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
+      if (row0 + r < M) {
+        const V av = __builtin_nontemporal_load(reinterpret_cast<const V*>(a + (row0 + r) * ld) + v);
+        acc[r] += vdot(av, xv);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    double s = acc[r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) red[wave][r] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kRowsPerWave && row0 + threadIdx.x < M) {
+    const int r = threadIdx.x;
+    y[row0 + r] = (T)(((red[0][r] + red[1][r]) + red[2][r]) + red[3][r]);
   }
 }
 
@@ -255,6 +306,16 @@ hipError_t launch_dense_forward(const pa_geometry* g, pa_dtype dt, const void* a
   if (d.P == 0) {   // y = 0
     if (dt == PA_F32) dense_zero_kernel<float><<<grid_for(M), kThreads, 0, st>>>(static_cast<float*>(y), M);
     else dense_zero_kernel<double><<<grid_for(M), kThreads, 0, st>>>(static_cast<double*>(y), M);
+    return hipGetLastError();
+  }
+  if (blocks < kSplitBelowBlocks) {   // too few rows to fill the chip: split each row's columns over four waves
+    const int64_t sblocks = (M + kRowsPerWave - 1) / kRowsPerWave;
+    if (dt == PA_F32)
+      dense_gemv_split_kernel<float><<<(unsigned)sblocks, kThreads, 0, st>>>(
+          static_cast<const float*>(a), static_cast<const float*>(x), static_cast<float*>(y), M, d.P, d.ld);
+    else
+      dense_gemv_split_kernel<double><<<(unsigned)sblocks, kThreads, 0, st>>>(
+          static_cast<const double*>(a), static_cast<const double*>(x), static_cast<double*>(y), M, d.P, d.ld);
     return hipGetLastError();
   }
   if (dt == PA_F32)
