@@ -73,6 +73,16 @@ def counter_summary():
     return rec if rec.get("kernel_sources_sha256") == kernel_sources_hash() else None
 
 
+def gpu_clocks():
+    """The current shader and memory clocks as rocm-smi reports them (empty when it is not there)."""
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=15).stdout
+    except (OSError, subprocess.SubprocessError):
+        return ""
+    keep = [ln.split(":", 2)[-1].strip() for ln in out.splitlines() if ("sclk" in ln or "mclk" in ln) and "GPU[" in ln]
+    return "; ".join(keep)
+
+
 def cpu_info():
     model = ""
     try:
@@ -125,6 +135,9 @@ def main():
     w = make_config("C2")
     g = w.geom
     geom = pa.DeviceGeometry(g, dev)
+    props = torch.cuda.get_device_properties(dev)
+    gpu = {"name": props.name, "arch": getattr(props, "gcnArchName", ""), "cus": props.multi_processor_count,
+           "clocks": gpu_clocks()}
     P, S, K = g.n_pixels, g.n_sensors, g.n_samples
     pairs = P * S
 
@@ -170,7 +183,7 @@ def main():
         "metric": METRIC, "value": iters_per_s, "unit": "CGLS iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded vessel-tree phantom, y = A x + 1% Gaussian noise)",
+        "data": "synthetic (seeded vessel-tree phantom, y = A x + 1% Gaussian noise)", "gpu": gpu,
         "config": {"workload": WORKLOAD, "image": [512, 512], "sensors": S, "samples": K,
                    "cgls_iterations": w.iters, "step": "one full CGLS solve (graph replay)",
                    "tuning": tuning},

@@ -87,6 +87,7 @@ __device__ __forceinline__ double vdot(const f64x2& a, const f64x2& b) { return 
 constexpr int kRowsPerWave = 4;
 constexpr int kRowsPerBlock = kRowsPerWave * (kThreads / 64);
 constexpr int64_t kSplitBelowBlocks = 2048;   // 16-row work-groups below which rows are split over waves
+constexpr int kColLoads = 8;                  // A^T: rows in flight per thread
 
 // y = A x: each wave owns four rows and streams them in 16-byte vectors, so
 // one load of x feeds four rows.  FP64 accumulation, wave-shuffle reduction
@@ -202,12 +203,12 @@ __global__ void __launch_bounds__(kThreads) dense_gemvt_partial_kernel(const T* 
     const V* col = reinterpret_cast<const V*>(a) + v;
     const int64_t ldv = ld / VN;
     int64_t m = m0;
-    for (; m + 4 <= m1; m += 4) {
-      V av[4];
+    for (; m + kColLoads <= m1; m += kColLoads) {   // kColLoads rows' loads in flight, added in row order
+      V av[kColLoads];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = __builtin_nontemporal_load(col + (m + u) * ldv);
+      for (int u = 0; u < kColLoads; ++u) av[u] = __builtin_nontemporal_load(col + (m + u) * ldv);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kColLoads; ++u) {
         const double w = (double)y[m + u];
         const T* e = reinterpret_cast<const T*>(&av[u]);
 #pragma unroll
