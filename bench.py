@@ -74,7 +74,10 @@ def counter_summary():
 
 
 def gpu_clocks():
-    """The current shader and memory clocks as rocm-smi reports them (empty when it is not there)."""
+    """The current shader and memory clocks as rocm-smi reports them (empty when it is not there, or
+    under a profiler, whose preloaded library would follow rocm-smi's own interpreter start)."""
+    if "rocprof" in os.environ.get("LD_PRELOAD", "") or any(k.startswith("ROCPROF") for k in os.environ):
+        return ""
     try:
         out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=15).stdout
     except (OSError, subprocess.SubprocessError):

@@ -33,8 +33,8 @@ constexpr size_t kLdsMax = 160 * 1024 - 1024;      // gfx950: 160 KiB of LDS per
 constexpr int kFwdList = kBlock;     // forward operator: base tiles listed per round (one per lane)
 constexpr int kSensorsPerFwdBlock = 64;          // partial-row forward: one sensor per lane of a wave
 constexpr size_t kLdsPreferredFwd = 80 * 1024;   // partial-row forward pass 1: two work-groups per CU
-constexpr size_t kLdsBatchFwd = 47 * 1024;       // batched sensor-major forward: with its ~1 KiB of static LDS
-                                                  // at most 48 KiB, three work-groups per CU
+constexpr size_t kLdsBatchFwd = 46 * 1024;       // batched sensor-major forward: with its 1 KiB of static
+                                                  // LDS within 48 KiB, three work-groups per CU
 
 // Arithmetic of a dtype: the type of every vector element (images, traces,
 // CGLS vectors) and of the per-pair delay and weight.
