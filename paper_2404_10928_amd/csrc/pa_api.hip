@@ -116,6 +116,39 @@ hipError_t enqueue_cgls(const Solve& S, hipStream_t st) {
     return pa::launch_adjoint(pl, r, s, &c2, st);
   };
   if ((e = adjoint_cg(alpha)) != hipSuccess) return e;
+  if (L.fused) {
+    // The direction update p_k = s_k + beta p_{k-1} (with gamma[k], history
+    // row k and the partials of ||p_k||^2) rides on pass 1 of q = A p_k; p_k
+    // alternates between two buffers.  The last history row comes from the
+    // direction kernel with no vector to update.
+    void* pb[2] = {p, ws + L.vec_p2};
+    for (int k = 0; k < S.iters; ++k) {
+      pa::CgDirArgs d{};
+      d.s = static_cast<const float*>(s);
+      d.p_old = static_cast<const float*>(pb[(k + 1) & 1]);
+      d.p_new = static_cast<float*>(pb[k & 1]);
+      d.part_s = part_s;
+      d.part_x = part_x;
+      d.part_r = part_r;
+      d.gs = gbp;
+      d.gx = gbp;
+      d.gr = L.g_m;
+      d.lambda = S.lambda;
+      d.gamma = gamma;
+      d.status = status;
+      d.hist = S.hist;
+      d.part_p = part_p;
+      d.k = k;
+      if ((e = pa::launch_forward_cg(pl, d, static_cast<float*>(q), part_q, fwd, st)) != hipSuccess) return e;
+      if ((e = pa::launch_upd_r(dt, r, q, pl.M, part_q, L.g_q, part_p, L.g_pf, S.lambda, gamma + k, alpha + k + 1,
+                                status, k, part_r, st)) != hipSuccess)
+        return e;
+      cg.p = pb[k & 1];
+      if ((e = adjoint_cg(alpha + k + 1)) != hipSuccess) return e;
+    }
+    return pa::launch_dir(dt, nullptr, s, 0, nullptr, 0, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma,
+                          S.iters - 1, status, S.hist, part_p, st);
+  }
   if ((e = pa::launch_dir(dt, p, s, pl.P, nullptr, 0, part_s, gbp, part_x, gbp, part_r, L.g_m, S.lambda, gamma, -1,
                           status, S.hist, part_p, st)) != hipSuccess)
     return e;

@@ -18,6 +18,29 @@ struct CgArgs {
   double* part_x;
 };
 
+// The CGLS direction update carried by the partial-row forward operator
+// (PA_F32): its pass 1 forms p_k = s_k + beta p_{k-1} while staging the
+// image, beta = ||s_k||^2 / gamma[k - 1] (0 for k = 0 or once the solve has
+// stopped), exactly as the separate direction kernel would; the work-groups
+// of the first sensor chunk write p_k and the FP64 partial sums of ||p_k||^2
+// (one per forward tile), and work-group 0 writes gamma[k] = ||s_k||^2 and
+// history row k.
+struct CgDirArgs {
+  const float* s;         // s_k
+  const float* p_old;     // p_{k-1} (not read for k = 0)
+  float* p_new;           // p_k
+  const double* part_s;   // partial sums of ||s_k||^2 ...
+  const double* part_x;   // ... of ||x_k||^2 ...
+  const double* part_r;   // ... and of ||r_k||^2
+  int gs, gx, gr;         // their counts
+  double lambda;
+  double* gamma;
+  const int* status;
+  double* hist;           // may be NULL
+  double* part_p;         // n_atiles partial sums of ||p_k||^2
+  int k;
+};
+
 hipError_t launch_fill(pa_dtype dt, void* p, int64_t n, hipStream_t st);
 // x := A^T y (or the CGLS epilogue when cg != nullptr)
 hipError_t launch_adjoint(const Plan& pl, const void* y, void* x, const CgArgs* cg, hipStream_t st);
@@ -26,6 +49,12 @@ hipError_t launch_adjoint(const Plan& pl, const void* y, void* x, const CgArgs* 
 // rows).  With plan.two_pass and a scratch of plan.fwd_scratch bytes the
 // partial-row method runs; otherwise the sensor-major one.
 hipError_t launch_forward(const Plan& pl, const void* x, void* y, double* part_q, void* scratch, hipStream_t st);
+// q := A p_k through partial rows with the direction update above folded into
+// pass 1 (x is not read: p_k is formed from dir.s and dir.p_old).  Only for
+// plans whose forward runs through partial rows (two_pass, fwd_scratch > 0,
+// fp2_grid > 0).
+hipError_t launch_forward_cg(const Plan& pl, const CgDirArgs& dir, float* q, double* part_q, void* scratch,
+                             hipStream_t st);
 hipError_t launch_init_r(pa_dtype dt, void* r, const void* y, const void* q, int64_t m, double* part_r, int* status,
                          double* alpha0, hipStream_t st);
 hipError_t launch_upd_r(pa_dtype dt, void* r, const void* q, int64_t m, const double* part_q, int gq, const double* part_p,

@@ -38,10 +38,10 @@ __global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restr
   fp_body<T, PH, ND, FRAC, FIX>(P, blockIdx.x, blockIdx.x, x, y, part_q);
 }
 
-template <int ND, bool FRAC>
+template <int ND, bool FRAC, bool CG>
 __global__ void __launch_bounds__(kBlock) fp2_kernel(OpParams P, const float* __restrict__ x, float* __restrict__ rows,
-                                                      int* __restrict__ klo_tab) {
-  fp2_body<ND, FRAC>(P, xcd_remap(blockIdx.x, gridDim.x), x, rows, klo_tab);
+                                                      int* __restrict__ klo_tab, CgDirArgs cg) {
+  fp2_body<ND, FRAC, CG>(P, xcd_remap(blockIdx.x, gridDim.x), x, rows, klo_tab, cg);
 }
 
 __global__ void __launch_bounds__(kBlock) fp_gather_kernel(OpParams P, const float* __restrict__ rows,
@@ -118,24 +118,30 @@ hipError_t launch_fwd_d(const Plan& pl, const void* x, void* y, double* part_q, 
   return pl.ndim == 2 ? launch_fp_f<T, PH, 2>(pl, x, y, part_q, st) : launch_fp_f<T, PH, 3>(pl, x, y, part_q, st);
 }
 
-template <int ND, bool FRAC>
-hipError_t launch_fp2_t(const Plan& pl, const float* x, float* rows, int* tab, hipStream_t st) {
-  auto kern = fp2_kernel<ND, FRAC>;
+template <int ND, bool FRAC, bool CG>
+hipError_t launch_fp2_t(const Plan& pl, const float* x, float* rows, int* tab, const CgDirArgs& cg, hipStream_t st) {
+  auto kern = fp2_kernel<ND, FRAC, CG>;
   hipError_t e = allow_lds(kern, pl.fp2_lds);
   if (e != hipSuccess) return e;
-  kern<<<pl.fp2_grid, kBlock, pl.fp2_lds, st>>>(pl.op, x, rows, tab);
+  kern<<<pl.fp2_grid, kBlock, pl.fp2_lds, st>>>(pl.op, x, rows, tab, cg);
   return hipGetLastError();
 }
 
+template <bool CG>
+hipError_t launch_fp2_f(const Plan& pl, const float* x, float* rows, int* tab, const CgDirArgs& cg, hipStream_t st) {
+  const bool frac = pl.op.t0f != 0.0f;
+  if (pl.ndim == 2)
+    return frac ? launch_fp2_t<2, true, CG>(pl, x, rows, tab, cg, st) : launch_fp2_t<2, false, CG>(pl, x, rows, tab, cg, st);
+  return frac ? launch_fp2_t<3, true, CG>(pl, x, rows, tab, cg, st) : launch_fp2_t<3, false, CG>(pl, x, rows, tab, cg, st);
+}
+
+// Pass 1 (with the direction update when cg != nullptr), then pass 2.
 hipError_t launch_forward_two_pass(const Plan& pl, const float* x, float* y, void* scratch, double* part_q,
-                                   hipStream_t st) {
+                                   const CgDirArgs* cg, hipStream_t st) {
   unsigned char* sc = static_cast<unsigned char*>(scratch);
   float* rows = reinterpret_cast<float*>(sc + pl.part_rows_off);
   int* tab = reinterpret_cast<int*>(sc + pl.klo_tab_off);
-  const bool frac = pl.op.t0f != 0.0f;
-  hipError_t e;
-  if (pl.ndim == 2) e = frac ? launch_fp2_t<2, true>(pl, x, rows, tab, st) : launch_fp2_t<2, false>(pl, x, rows, tab, st);
-  else e = frac ? launch_fp2_t<3, true>(pl, x, rows, tab, st) : launch_fp2_t<3, false>(pl, x, rows, tab, st);
+  hipError_t e = cg ? launch_fp2_f<true>(pl, x, rows, tab, *cg, st) : launch_fp2_f<false>(pl, x, rows, tab, CgDirArgs{}, st);
   if (e != hipSuccess) return e;
   fp_gather_kernel<<<pl.gather_grid, kBlock, 0, st>>>(pl.op, rows, tab, y, part_q);
   return hipGetLastError();
@@ -158,12 +164,18 @@ hipError_t launch_forward(const Plan& pl, const void* x, void* y, double* part_q
     return launch_fill(PA_F64, part_q, 1, st);
   }
   if (pl.two_pass && scratch && pl.fwd_scratch > 0)
-    return launch_forward_two_pass(pl, static_cast<const float*>(x), static_cast<float*>(y), scratch, part_q, st);
+    return launch_forward_two_pass(pl, static_cast<const float*>(x), static_cast<float*>(y), scratch, part_q, nullptr, st);
   switch (pl.dtype) {
     case PA_F32: return launch_fwd_d<float, float>(pl, x, y, part_q, st);
     case PA_MIXED: return launch_fwd_d<double, float>(pl, x, y, part_q, st);
     default: return launch_fwd_d<double, double>(pl, x, y, part_q, st);
   }
+}
+
+hipError_t launch_forward_cg(const Plan& pl, const CgDirArgs& dir, float* q, double* part_q, void* scratch,
+                             hipStream_t st) {
+  if (!(pl.two_pass && scratch && pl.fwd_scratch > 0 && pl.fp2_grid > 0 && pl.dtype == PA_F32)) return hipErrorInvalidValue;
+  return launch_forward_two_pass(pl, nullptr, q, scratch, part_q, &dir, st);
 }
 
 }  // namespace pa

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "pa_device.h"
+#include "pa_kernels.h"
 #include "pa_plan.h"
 
 namespace pa {
@@ -477,26 +478,31 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
     }
     __syncthreads();
     // Stage the windows: wave w copies rows w, w+4, ... (row parameters are
-    // wave-uniform), four rows' loads in flight before their stores.
+    // wave-uniform), 64 samples of a row per step, with the loads of eight
+    // rows in flight before their stores (every load is issued, from the
+    // first sample of the data where the row has none, and the unused ones
+    // dropped).
+    constexpr int RB = 8;
     for (int i0 = 0; i0 < P.wp; i0 += 64) {
       const int i = i0 + lane;
-      for (int j0 = wave; j0 < nsc; j0 += 16) {
-        T v[4];
+      for (int j0 = wave; j0 < nsc; j0 += 4 * RB) {
+        T v[RB];
+        unsigned okb = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < RB; ++u) {
           const int j = j0 + 4 * u;
-          v[u] = 0;
-          if (j < nsc) {
-            const int kl = __builtin_amdgcn_readfirstlane(klo_s[j]);
-            const int sj = __builtin_amdgcn_readfirstlane(sid[j]);
-            const int k = kl + i;
-            if (i < P.wp && k >= 0 && k < P.K) v[u] = y[(size_t)sj * P.K + k];
-          }
+          const int jj = j < nsc ? j : 0;
+          const int kl = __builtin_amdgcn_readfirstlane(klo_s[jj]);
+          const int sj = __builtin_amdgcn_readfirstlane(sid[jj]);
+          const int k = kl + i;
+          const bool ok = j < nsc && i < P.wp && k >= 0 && k < P.K;
+          okb |= ok ? 1u << u : 0u;
+          v[u] = P.K > 0 ? y[ok ? (size_t)sj * P.K + k : 0] : (T)0;   // (no trace at all: nothing to read)
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < RB; ++u) {
           const int j = j0 + 4 * u;
-          if (j < nsc && i < P.wp) win[j * P.wp + i] = v[u];
+          if (j < nsc && i < P.wp) win[j * P.wp + i] = (okb >> u) & 1u ? v[u] : (T)0;
         }
       }
     }
@@ -946,9 +952,9 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
 // taps into its own sensor's LDS histogram row, so the lanes of one ds_add
 // never collide on an address.  The rows are then written out with plain
 // coalesced stores, with the first sample of each row in a table.
-template <int ND, bool FRAC>
+template <int ND, bool FRAC, bool CG>
 __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* __restrict__ x, float* __restrict__ rows,
-                                         int* __restrict__ klo_tab) {
+                                         int* __restrict__ klo_tab, const CgDirArgs& cg) {
   using T = float;
   using SC = SC32;
   using PX = Pix32;
@@ -970,6 +976,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   int* klo_a = reinterpret_cast<int*>(smem + L.klo);
   double* inv_a = reinterpret_cast<double*>(smem + L.inv);
   __shared__ double red[4];
+  __shared__ double ppw[4];   // per-wave sums of p_k^2 (direction update)
 
   // chunk-major: with the XCD remap of the launch, each XCD takes a
   // contiguous run of (chunk, tile) blocks, so one chunk's rows are written
@@ -985,24 +992,122 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   const int s = chunk * NS + lane;
   const bool s_ok = s < P.S;
 
-  // pixel offsets of a base tile (same for every base tile) and the forward tile's x values
+  // this lane's sensor (its load goes out with the x loads below)
+  double sp[3];
+  sensor_pos<ND>(P, s_ok ? s : P.S - 1, sp);
+  double* sa_m = reinterpret_cast<double*>(smem + L.inv) + NS;  // [nsub][4] per-wave sums of |x|
+  // The forward tile's x values, staged in LDS, and each wave's sum of |x|
+  // over its 64 pixels of every base tile.  Base tiles go in groups of four:
+  // a group's global loads are all issued before the first is used, and its
+  // four wave sums share the shuffle steps.  With the CGLS direction update
+  // the staged values are p_k = s_k + beta p_{k-1} (the first two groups'
+  // loads of s and p go out before beta is formed), the first sensor chunk
+  // writes them out, and each thread sums its p_k^2.
   bool nfx = false;   // a NaN or infinite x among this lane's staged values
+  double pp = 0.0;
   {
+    constexpr int MG = 4, NB = 2 * MG;
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    for (int m = 0; m < P.nsub; ++m) {
+    // element index of this thread's pixel of base tile m, -1 outside the image
+    auto pix_index = [&](int m) -> int64_t {
       const int bx = ax * P.msub[0] + m % P.msub[0];
       const int by = ay * P.msub[1] + (m / P.msub[0]) % P.msub[1];
       const int bz = az * P.msub[2] + m / (P.msub[0] * P.msub[1]);
       const int ix = bx * TX + lx, iy = by * TY + ly, iz = bz * TZ + lz;
-      T v = 0;
-      if (ix < P.nx && iy < P.ny && iz < P.nz) v = x[((size_t)iz * P.ny + iy) * P.nx + ix];
-      nfx |= non_finite_bits(v);
-      xs[m * kBlock + tid] = v;
+      return m < P.nsub && ix < P.nx && iy < P.ny && iz < P.nz ? ((int64_t)iz * P.ny + iy) * P.nx + ix : -1;
+    };
+    auto stage = [&](int m0, const T (&v)[MG]) {
+      double a[MG];
+#pragma unroll
+      for (int u = 0; u < MG; ++u) {
+        nfx |= non_finite_bits(v[u]);
+        if (m0 + u < P.nsub) xs[(m0 + u) * kBlock + tid] = v[u];
+        a[u] = fabs((double)v[u]);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int u = 0; u < MG; ++u) a[u] += __shfl_xor(a[u], o, 64);
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < MG; ++u)
+          if (m0 + u < P.nsub) sa_m[(m0 + u) * 4 + wave] = a[u];
+      }
+    };
+    if constexpr (CG) {
+      const bool rp = cg.k >= 1;   // p_{k-1} is read
+      int64_t ib[NB];
+      T sv[NB], pv[NB];
+#pragma unroll
+      for (int m = 0; m < NB; ++m) {
+        ib[m] = pix_index(m);
+        sv[m] = ib[m] >= 0 ? cg.s[ib[m]] : (T)0;
+        pv[m] = rp && ib[m] >= 0 ? cg.p_old[ib[m]] : (T)0;
+      }
+      // beta = ||s_k||^2 / gamma[k - 1]: the same sum, in the same order, in
+      // every work-group
+      const double ss = dev::sum_partials(cg.part_s, cg.gs, red);
+      double beta = 0.0;
+      if (rp) {
+        const double gold = cg.gamma[cg.k - 1];
+        beta = (*cg.status >= 0 || !(gold > 0.0)) ? 0.0 : ss / gold;
+      }
+      if (blockIdx.x == 0) {   // gamma[k] and history row k, once
+        const double xx = dev::sum_partials(cg.part_x, cg.gx, red);
+        const double rr = dev::sum_partials(cg.part_r, cg.gr, red);
+        if (tid == 0) {
+          cg.gamma[cg.k] = ss;
+          if (cg.hist) {
+            cg.hist[3 * cg.k + 0] = sqrt(rr);
+            cg.hist[3 * cg.k + 1] = sqrt(ss);
+            cg.hist[3 * cg.k + 2] = rr + cg.lambda * xx;
+          }
+        }
+      }
+      auto dirv = [&](int64_t i, T sk, T pk) -> T {
+        if (i < 0) return (T)0;
+        const T t = (T)((double)sk + (beta != 0.0 ? beta * (double)pk : 0.0));
+        if (chunk == 0) cg.p_new[i] = t;
+        pp += (double)t * (double)t;
+        return t;
+      };
+#pragma unroll
+      for (int g = 0; g < NB / MG; ++g) {
+        if (g * MG < P.nsub) {
+          T v[MG];
+#pragma unroll
+          for (int u = 0; u < MG; ++u) v[u] = dirv(ib[g * MG + u], sv[g * MG + u], pv[g * MG + u]);
+          stage(g * MG, v);
+        }
+      }
+      for (int m0 = NB; m0 < P.nsub; m0 += MG) {
+        int64_t i2[MG];
+        T s2[MG], p2[MG], v[MG];
+#pragma unroll
+        for (int u = 0; u < MG; ++u) {
+          i2[u] = pix_index(m0 + u);
+          s2[u] = i2[u] >= 0 ? cg.s[i2[u]] : (T)0;
+          p2[u] = rp && i2[u] >= 0 ? cg.p_old[i2[u]] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < MG; ++u) v[u] = dirv(i2[u], s2[u], p2[u]);
+        stage(m0, v);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) pp += __shfl_xor(pp, o, 64);
+      if (lane == 0) ppw[wave] = pp;
+    } else {
+      for (int m0 = 0; m0 < P.nsub; m0 += MG) {
+        T v[MG];
+#pragma unroll
+        for (int u = 0; u < MG; ++u) {
+          const int64_t i = pix_index(m0 + u);
+          v[u] = i >= 0 ? x[i] : (T)0;
+        }
+        stage(m0, v);
+      }
     }
   }
-  // this lane's sensor
-  double sp[3];
-  sensor_pos<ND>(P, s_ok ? s : P.S - 1, sp);
   // Fixed-point scale: a tap of pixel p in base tile m is at most
   // |x_p| / (2 dmin_m), dmin_m being the distance from this lane's sensor to
   // base tile m (clamped at r_min), so B_s = sum_m (sum_{p in m} |x_p|) /
@@ -1010,16 +1115,12 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   // same 64 sensors, so the FP64 per-sensor work is split between them: wave
   // w forms the terms of base tiles w, w + 4, ..., wave 0 the window over the
   // forward tile, and wave 0 adds the terms in tile order.
-  double* sa_m = reinterpret_cast<double*>(smem + L.inv) + NS;  // [nsub][4] per-wave sums of |x|
   double* bterm = sa_m + 4 * P.nsub;                              // [nsub][64] bound terms
   float* scl_a = reinterpret_cast<float*>(bterm + P.nsub * NS);   // [64] fixed-point scales
-  for (int m = 0; m < P.nsub; ++m) {
-    double v = fabs((double)xs[m * kBlock + tid]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) sa_m[m * 4 + wave] = v;
+  const bool tile_nf = __syncthreads_or(nfx) != 0;   // (also the barrier for sa_m and ppw)
+  if constexpr (CG) {
+    if (chunk == 0 && tid == 0) cg.part_p[at] = (ppw[0] + ppw[1]) + (ppw[2] + ppw[3]);
   }
-  const bool tile_nf = __syncthreads_or(nfx) != 0;   // (also the barrier for sa_m)
   // Tiny x (the forward tile's sum below ~1e-18): scale the staged values
   // by an exact power of two, so 2^30 / B_s stays finite and the fixed
   // point keeps its full range; the rows are scaled back on the way out.
@@ -1201,13 +1302,32 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   }
   __syncthreads();
 
-  // histogram rows out, row (sensor, forward tile) at ((s * n_atiles) + at) * wpa
-  for (int j = wave; j < NS; j += 4) {
-    const int sj = chunk * NS + j;
-    if (sj >= P.S) break;
-    T* row = rows + ((size_t)sj * P.n_atiles + at) * P.wpa;
-    const double inv = inv_a[j];
-    for (int i = lane; i < P.wpa; i += 64) row[i] = (T)((double)hist[j * P.wpa + i] * inv);
+  // histogram rows out, row (sensor, forward tile) at ((s * n_atiles) + at) * wpa:
+  // wave w takes rows w, w + 4, ..., 64 samples of a row per step, with the
+  // LDS reads of eight rows issued before their conversions and stores; a
+  // row's scale comes from the lane that holds it
+  {
+    constexpr int RB = 8;
+    const double inv_l = inv_a[lane];
+    const int nrw = (min(NS, P.S - chunk * NS) - wave + 3) >> 2;   // this wave's rows
+    for (int i = lane; i - lane < P.wpa; i += 64) {
+      const bool iok = i < P.wpa;
+      for (int r0 = 0; r0 < nrw; r0 += RB) {
+        H hv[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u)   // unconditional reads (bin 0 in place of the missing ones)
+          hv[u] = hist[iok && r0 + u < nrw ? (wave + 4 * (r0 + u)) * P.wpa + i : 0];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          const int j = wave + 4 * (r0 + u);
+          if (r0 + u < nrw) {   // wave-uniform
+            const double inv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(inv_l), j),
+                                                __builtin_amdgcn_readlane(__double2loint(inv_l), j));
+            if (iok) rows[((size_t)(chunk * NS + j) * P.n_atiles + at) * P.wpa + i] = (T)((double)hv[u] * inv);
+          }
+        }
+      }
+    }
   }
   if (wave == 0 && s_ok) klo_tab[(size_t)s * P.n_atiles + at] = klo_a[lane];
 }

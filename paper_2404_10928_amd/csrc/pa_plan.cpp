@@ -324,6 +324,8 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   L.g_m = blas_grid(plan.M);
   L.g_p = blas_grid(plan.P);
   L.g_bp = std::max(plan.op.n_tiles, 1);
+  L.fused = plan.dtype == PA_F32 && plan.two_pass && plan.fwd_scratch > 0 && plan.fp2_grid > 0 && plan.P > 0;
+  L.g_pf = L.fused ? std::max(plan.op.n_atiles, 1) : 0;
   size_t off = 0;
   L.status = off; off = align_up(off + 64, A);
   L.gamma = off; off = align_up(off + sizeof(double) * (size_t)(iters + 2), A);
@@ -332,11 +334,12 @@ CglsLayout cgls_layout(const Plan& plan, int32_t iters) {
   L.part_r = off; off = align_up(off + sizeof(double) * L.g_m, A);
   L.part_s = off; off = align_up(off + sizeof(double) * L.g_bp, A);
   L.part_x = off; off = align_up(off + sizeof(double) * L.g_bp, A);
-  L.part_p = off; off = align_up(off + sizeof(double) * L.g_p, A);
+  L.part_p = off; off = align_up(off + sizeof(double) * std::max(L.g_p, L.g_pf), A);
   L.vec_r = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
   L.vec_q = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.M, 1), A);
   L.vec_s = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
   L.vec_p = off; off = align_up(off + plan.elem * (size_t)std::max<int64_t>(plan.P, 1), A);
+  L.vec_p2 = off; off = align_up(off + (L.fused ? plan.elem * (size_t)plan.P : 0), A);
   L.fwd = off; off = align_up(off + (plan.two_pass ? plan.fwd_scratch : 0), A);
   L.total = off;
   return L;

@@ -262,8 +262,10 @@ int blas_grid(int64_t n);
 
 // CGLS workspace layout.
 struct CglsLayout {
-  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, fwd, total;
+  size_t status, gamma, alpha, part_q, part_r, part_s, part_x, part_p, vec_r, vec_q, vec_s, vec_p, vec_p2, fwd, total;
   int g_q, g_m, g_p, g_bp;  // partial counts: forward work-groups, over S*K, over pixels, adjoint tiles
+  bool fused;               // the direction update rides on the partial-row forward (p alternates vec_p, vec_p2)
+  int g_pf;                 // ... and ||p||^2 then has one partial per forward tile
 };
 CglsLayout cgls_layout(const Plan& plan, int32_t iters);
 
