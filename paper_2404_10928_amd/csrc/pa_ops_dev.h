@@ -342,12 +342,12 @@ __device__ __forceinline__ bool non_finite_bits(double v) {
   return (b & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
 }
 
-// floor(v + 0.5) as an int in one instruction (round half up; the two taps of
-// a pair are rounded the same way, so they still sum to the rounded total).
+// floor(v + 0.5) as an int (round half up; the two taps of a pair are rounded
+// the same way, so they still sum to the rounded total).  Under the operator
+// files' build flags (no IEEE mode, no NaNs) this is one v_cvt_rpi_i32_f32,
+// which the scheduler can move like any other instruction.
 __device__ __forceinline__ int round_i(float v) {
-  int r;
-  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-  return r;
+  return (int)__builtin_floorf(v + 0.5f);
 }
 
 // Sum over the 64 lanes of a wave with DPP moves (no LDS round trips), in a
