@@ -67,12 +67,16 @@ __device__ __forceinline__ void upd_r_body(int bid, int nblk, T* __restrict__ r,
   // known, so their latency overlaps the partial sums.
   const int64_t stride = (int64_t)nblk * kBlock;
   const int64_t i0 = (int64_t)bid * kBlock + threadIdx.x;
+  // (every load is issued, element 0 in place of one past the end, so they
+  // go out back to back; the extra values are never used)
   T rv[kPrefetch], qv[kPrefetch];
+  if (m > 0) {
 #pragma unroll
-  for (int u = 0; u < kPrefetch; ++u) {
-    const int64_t i = i0 + u * stride;
-    rv[u] = i < m ? r[i] : (T)0;
-    qv[u] = i < m ? q[i] : (T)0;
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int64_t i = i0 + u * stride;
+      rv[u] = r[i < m ? i : 0];
+      qv[u] = q[i < m ? i : 0];
+    }
   }
   double sums[2];
   dev::sum_partials_n<2>({part_q, part_p}, {gq, gp}, sums, red);
@@ -126,12 +130,15 @@ __device__ __forceinline__ void dir_body(int bid, int nblk, T* __restrict__ p, c
   // The first kPrefetch elements' loads go out before beta is known.
   const int64_t stride = (int64_t)nblk * kBlock;
   const int64_t i0 = (int64_t)bid * kBlock + threadIdx.x;
+  // (loads issued back to back, as in upd_r_body)
   T sv[kPrefetch], pv[kPrefetch];
+  if (np > 0) {
 #pragma unroll
-  for (int u = 0; u < kPrefetch; ++u) {
-    const int64_t i = i0 + u * stride;
-    sv[u] = i < np ? s[i] : (T)0;
-    pv[u] = i < np ? p[i] : (T)0;
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int64_t i = i0 + u * stride;
+      sv[u] = s[i < np ? i : 0];
+      pv[u] = p[i < np ? i : 0];
+    }
   }
   double sums[3];
   dev::sum_partials_n<3>({part_s, part_x, part_r}, {gs, gx, gr}, sums, red);
@@ -468,14 +475,12 @@ hipError_t launch_lw_final(const double* part_r, int gr, const double* part_x, i
 // dx/m of the pixel to the left, dy/m of the pixel above and -(dx + dy)/m of
 // p itself.  Every per-pixel value is formed in FP64 from the stored z.
 
-// Forward differences of z at (ix, iy) and their m.
-template <typename T>
-__device__ __forceinline__ double tv_m(const T* __restrict__ z, int ix, int iy, int nx, int ny, double eps2,
+// Forward differences at a pixel of value zp from its right (zr) and lower
+// (zd) neighbours, zero across the image's far edges, and their m.
+__device__ __forceinline__ double tv_m(double zp, double zr, double zd, bool has_r, bool has_d, double eps2,
                                        double* dx, double* dy) {
-  const int64_t p = (int64_t)iy * nx + ix;
-  const double zp = (double)z[p];
-  *dx = ix + 1 < nx ? (double)z[p + 1] - zp : 0.0;
-  *dy = iy + 1 < ny ? (double)z[p + nx] - zp : 0.0;
+  *dx = has_r ? zr - zp : 0.0;
+  *dy = has_d ? zd - zp : 0.0;
   return sqrt(*dx * *dx + *dy * *dy + eps2);
 }
 
@@ -501,28 +506,42 @@ __global__ void __launch_bounds__(kBlock) fista_step_kernel(const T* __restrict_
   const double eps2 = eps * eps;
   double acc_tv = 0.0, acc_l1 = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < np; i += (int64_t)gridDim.x * kBlock) {
-    const double zi = (double)z[i];
+    // every value this pixel needs is loaded up front (a neighbour across an
+    // edge reads the pixel itself and is not used), so the loads go out
+    // back to back
+    const T zi_t = z[i], si_t = s[i], xi_t = x[i];
+    const int ix = (int)(i % nx), iy = (int)(i / nx);
+    const bool r = ix + 1 < nx, d = iy + 1 < ny, l = ix > 0, u = iy > 0;
+    T zr = zi_t, zd = zi_t, zl = zi_t, zld = zi_t, zu = zi_t, zur = zi_t;
+    if (beta != 0.0) {
+      zr = z[r ? i + 1 : i];
+      zd = z[d ? i + nx : i];
+      zl = z[l ? i - 1 : i];
+      zld = z[l && d ? i - 1 + nx : i];
+      zu = z[u ? i - nx : i];
+      zur = z[u && r ? i - nx + 1 : i];
+    }
+    const double zi = (double)zi_t;
     acc_l1 += fabs(zi);
     double gtv = 0.0;
     if (beta != 0.0) {
-      const int ix = (int)(i % nx), iy = (int)(i / nx);
       double dx, dy, ex, ey;
-      const double m = tv_m(z, ix, iy, nx, ny, eps2, &dx, &dy);
+      const double m = tv_m(zi, (double)zr, (double)zd, r, d, eps2, &dx, &dy);
       acc_tv += m;
       gtv = -(dx + dy) / m;
-      if (ix > 0) {
-        const double ml = tv_m(z, ix - 1, iy, nx, ny, eps2, &ex, &ey);
+      if (l) {   // the left neighbour's differences (its right neighbour is this pixel)
+        const double ml = tv_m((double)zl, zi, (double)zld, true, d, eps2, &ex, &ey);
         gtv += ex / ml;
       }
-      if (iy > 0) {
-        const double mu_ = tv_m(z, ix, iy - 1, nx, ny, eps2, &ex, &ey);
+      if (u) {   // the upper neighbour's (its lower neighbour is this pixel)
+        const double mu_ = tv_m((double)zu, (double)zur, zi, r, true, eps2, &ex, &ey);
         gtv += ey / mu_;
       }
     }
-    const double v = zi + w * ((double)s[i] - 0.5 * beta * gtv);
+    const double v = zi + w * ((double)si_t - 0.5 * beta * gtv);
     const T xn = (T)shrink(v, tau, nonneg);
     const double xd = (double)xn;
-    zn[i] = (T)(xd + mu * (xd - (double)x[i]));
+    zn[i] = (T)(xd + mu * (xd - (double)xi_t));
     x[i] = xn;
   }
   acc_tv = block_sum(acc_tv, red);
@@ -544,12 +563,20 @@ __global__ void __launch_bounds__(kBlock) fista_terms_kernel(const T* __restrict
   const double eps2 = eps * eps;
   double a2 = 0.0, atv = 0.0, a1 = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < np; i += (int64_t)gridDim.x * kBlock) {
-    const double t = (double)v[i];
+    const T vi = v[i];
+    const int ix = (int)(i % nx), iy = (int)(i / nx);
+    const bool r = ix + 1 < nx, d = iy + 1 < ny;
+    T vr = vi, vd = vi;
+    if (beta != 0.0) {   // (loaded together; across an edge, the pixel itself)
+      vr = v[r ? i + 1 : i];
+      vd = v[d ? i + nx : i];
+    }
+    const double t = (double)vi;
     a2 += t * t;
     a1 += fabs(t);
     if (beta != 0.0) {
       double dx, dy;
-      atv += tv_m(v, (int)(i % nx), (int)(i / nx), nx, ny, eps2, &dx, &dy);
+      atv += tv_m(t, (double)vr, (double)vd, r, d, eps2, &dx, &dy);
     }
   }
   a2 = block_sum(a2, red);

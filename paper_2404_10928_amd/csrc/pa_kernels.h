@@ -27,7 +27,7 @@ struct CgArgs {
 // history row k.
 struct CgDirArgs {
   const float* s;         // s_k
-  const float* p_old;     // p_{k-1} (not read for k = 0)
+  const float* p_old;     // p_{k-1} (for k = 0, any P readable floats: beta is 0)
   float* p_new;           // p_k
   const double* part_s;   // partial sums of ||s_k||^2 ...
   const double* part_x;   // ... of ||x_k||^2 ...

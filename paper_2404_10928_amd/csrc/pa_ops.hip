@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restr
 }
 
 template <int ND, bool FRAC, bool CG>
-__global__ void __launch_bounds__(kBlock) fp2_kernel(OpParams P, const float* __restrict__ x, float* __restrict__ rows,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) fp2_kernel(OpParams P, const float* __restrict__ x, float* __restrict__ rows,
                                                       int* __restrict__ klo_tab, CgDirArgs cg) {
   fp2_body<ND, FRAC, CG>(P, xcd_remap(blockIdx.x, gridDim.x), x, rows, klo_tab, cg);
 }

@@ -1041,8 +1041,10 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
 #pragma unroll
       for (int m = 0; m < NB; ++m) {
         ib[m] = pix_index(m);
-        sv[m] = ib[m] >= 0 ? cg.s[ib[m]] : (T)0;
-        pv[m] = rp && ib[m] >= 0 ? cg.p_old[ib[m]] : (T)0;
+        // (unconditional loads, element 0 for pixels outside: they go out
+        // back to back, and dirv() drops the extra values)
+        sv[m] = cg.s[ib[m] >= 0 ? ib[m] : 0];
+        pv[m] = cg.p_old[ib[m] >= 0 ? ib[m] : 0];   // (read also for k = 0: beta is 0 then)
       }
       // beta = ||s_k||^2 / gamma[k - 1]: the same sum, in the same order, in
       // every work-group
@@ -1086,8 +1088,8 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
 #pragma unroll
         for (int u = 0; u < MG; ++u) {
           i2[u] = pix_index(m0 + u);
-          s2[u] = i2[u] >= 0 ? cg.s[i2[u]] : (T)0;
-          p2[u] = rp && i2[u] >= 0 ? cg.p_old[i2[u]] : (T)0;
+          s2[u] = cg.s[i2[u] >= 0 ? i2[u] : 0];
+          p2[u] = cg.p_old[i2[u] >= 0 ? i2[u] : 0];
         }
 #pragma unroll
         for (int u = 0; u < MG; ++u) v[u] = dirv(i2[u], s2[u], p2[u]);
@@ -1333,11 +1335,11 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
 }
 
 // A through partial rows, pass 2: one work-group per (sensor, segment of kseg <= 256 samples),
-// one sample per lane.  Each wave scans the window starts of the sensor's
-// forward tiles, 64 at a time, picks by ballot the tiles whose row window
+// one sample per lane.  Each wave loads the window starts of the sensor's
+// forward tiles, 256 at a time, picks by ballot the tiles whose row window
 // overlaps its own 64 samples, and every lane adds its sample of those rows,
-// in increasing tile order, in FP64 (kGatherLoads loads in flight, the next 64
-// window starts prefetched); then the work-group scales, writes y and forms
+// in increasing tile order, in FP64 (kGatherLoads loads in flight, taken
+// across the 256 tiles); then the work-group scales, writes y and forms
 // the FP64 partial of ||y||^2.  No atomics: the result is the same on every
 // run.  Rows and window starts are sensor-major, so one sensor's rows are
 // contiguous.  The launch remaps work-groups so each XCD takes a contiguous
@@ -1365,29 +1367,61 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
   const int wlo = k0 + wave * 64, whi = min(k0 + kn, wlo + 64);  // this wave's samples
   double acc = 0.0;
   if (wlo < whi) {
-    // window starts of the next 64 tiles are loaded while this chunk's rows are read
-    int kl_next = lane < P.n_atiles ? kt[lane] : 0;
-    for (int c0 = 0; c0 < P.n_atiles; c0 += 64) {
-      const int t = c0 + lane;
-      const int kl = kl_next;
-      const bool ov = t < P.n_atiles && kl < whi && kl + P.wpa > wlo;
-      if (t + 64 < P.n_atiles) kl_next = kt[t + 64];
-      uint64_t m = __ballot(ov);
-      while (m != 0) {
-        double v[kGatherLoads];
+    // Tiles go in groups of 256: the window starts of a group are loaded
+    // together (four per lane, tile g0 + 64 c + lane), the four ballots pick
+    // the tiles whose row overlaps this wave's samples, and the rows are read
+    // kGatherLoads at a time across the group, in increasing tile order.
+    for (int g0 = 0; g0 < P.n_atiles; g0 += 256) {
+      int kl[4];
+      uint64_t m[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int t = g0 + 64 * c + lane;
+        kl[c] = t < P.n_atiles ? kt[t] : 0;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int t = g0 + 64 * c + lane;
+        m[c] = __ballot(t < P.n_atiles && kl[c] < whi && kl[c] + P.wpa > wlo);
+      }
+      // m[0] and kl[0] belong to chunk c, the chunk of the next pick
+      // (wave-uniform); advance() moves on to the next chunk with picks
+      int c = 0;
+      auto advance = [&]() {
+        while (c < 4 && m[0] == 0) {
+          m[0] = m[1];
+          m[1] = m[2];
+          m[2] = m[3];
+          m[3] = 0;
+          kl[0] = kl[1];
+          kl[1] = kl[2];
+          kl[2] = kl[3];
+          ++c;
+        }
+      };
+      advance();
+      while (c < 4) {
+        // every lane loads (its own sample of the row, else the row's first
+        // sample), so the loads go out back to back; the unused values are
+        // dropped when they are added
+        float v[kGatherLoads];
+        unsigned okm = 0;
 #pragma unroll
         for (int u = 0; u < kGatherLoads; ++u) {
-          v[u] = 0.0;
-          if (m != 0) {  // wave-uniform
-            const int b = __builtin_ctzll(m);
-            m &= m - 1;
-            const int klb = __builtin_amdgcn_readlane(kl, b);
+          v[u] = 0.f;
+          if (c < 4) {   // wave-uniform
+            const int b = __builtin_ctzll(m[0]);
+            m[0] &= m[0] - 1;
+            const int klb = __builtin_amdgcn_readlane(kl[0], b);
             const int j = k - klb;
-            if (k_ok && j >= 0 && j < P.wpa) v[u] = (double)srow[(size_t)(c0 + b) * P.wpa + j];
+            const bool ok = k_ok && j >= 0 && j < P.wpa;
+            okm |= ok ? 1u << u : 0u;
+            v[u] = srow[(size_t)(g0 + 64 * c + b) * P.wpa + (ok ? j : 0)];
+            advance();
           }
         }
 #pragma unroll
-        for (int u = 0; u < kGatherLoads; ++u) acc += v[u];
+        for (int u = 0; u < kGatherLoads; ++u) acc += (okm >> u) & 1u ? (double)v[u] : 0.0;
       }
     }
   }
