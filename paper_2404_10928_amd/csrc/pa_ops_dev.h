@@ -284,12 +284,18 @@ __device__ __forceinline__ void phase_near(const Near32& n, const double o[3], d
     R2 = R2 + dz * dz;
   }
   R2 = fmax(R2, rmin2);
-  const double R = sqrt(R2);
+  // R from the hardware reciprocal square root and one Newton step (relative
+  // error ~1e-14, far below what the delay's fraction needs); the weight,
+  // an FP32 value, from the FP32 one, as in the far pairs' arithmetic
+  const double y0 = __builtin_amdgcn_rsq(R2);
+  const double hy = 0.5 * R2 * y0;
+  const double y1 = fma(y0, fma(-hy, y0, 0.5), y0);
+  const double R = R2 > 0.0 ? R2 * y1 : 0.0;   // (a pixel on the sensor with r_min = 0: R = 0, an infinite weight)
   double d = R - n.KR;
   if (FRAC) d = d - t0fd;
   const double fl = floor(d);
   f = (float)(d - fl);
-  wt = (float)((double)half / R);
+  wt = half * __builtin_amdgcn_rsqf((float)R2);
   kbyte = (int)fl * ESZ + base;
 }
 
