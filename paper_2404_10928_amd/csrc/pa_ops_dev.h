@@ -356,6 +356,19 @@ __device__ __forceinline__ int round_i(float v) {
   return (int)__builtin_floorf(v + 0.5f);
 }
 
+// Wave priority from progress q = 0, 1, 2, 3 (quarters of a work-group's main
+// loop done): 3, 2, 1, 0.  The instruction arbiter favours the oldest waves,
+// so without this the work-groups sharing a CU (the whole grid is one round)
+// run their loops one after another and the last one finishes alone, with
+// one wave per SIMD left to issue; lowering a wave's priority as it gets
+// ahead keeps the CU's work-groups level and its VALU busy to the end.
+__device__ __forceinline__ void progress_prio(int q) {
+  if (q <= 0) __builtin_amdgcn_s_setprio(3);
+  else if (q == 1) __builtin_amdgcn_s_setprio(2);
+  else if (q == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 // Sum over the 64 lanes of a wave with DPP moves (no LDS round trips), in a
 // fixed order; every lane gets the total.
 template <int CTRL>
@@ -441,6 +454,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
 
   T acc = 0;
   for (int s0 = 0; s0 < P.S; s0 += P.sc) {
+    progress_prio((4 * s0) / P.S);
     const int nsc = min(P.sc, P.S - s0);
     const bool mine = tid < nsc;
     double sp[3] = {0.0, 0.0, 0.0};
@@ -1042,6 +1056,9 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     };
     if constexpr (CG) {
       const bool rp = cg.k >= 1;   // p_{k-1} is read
+      // the scalars beta needs go out first, with the vector loads below
+      const int st_k = *cg.status;
+      const double gold = cg.gamma[rp ? cg.k - 1 : 0];
       int64_t ib[NB];
       T sv[NB], pv[NB];
 #pragma unroll
@@ -1056,10 +1073,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
       // every work-group
       const double ss = dev::sum_partials(cg.part_s, cg.gs, red);
       double beta = 0.0;
-      if (rp) {
-        const double gold = cg.gamma[cg.k - 1];
-        beta = (*cg.status >= 0 || !(gold > 0.0)) ? 0.0 : ss / gold;
-      }
+      if (rp) beta = (st_k >= 0 || !(gold > 0.0)) ? 0.0 : ss / gold;
       if (blockIdx.x == 0) {   // gamma[k] and history row k, once
         const double xx = dev::sum_partials(cg.part_x, cg.gx, red);
         const double rr = dev::sum_partials(cg.part_r, cg.gr, red);
@@ -1266,6 +1280,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     };
     load4(pa_, xa_);
     for (int p = p_lo; p < p_hi; p += 8) {
+      if (((p - p_lo) & 63) == 0) progress_prio(((p - p_lo) * 4) / (p_hi - p_lo));
       load4(pb_, xb_);
       scatter4(pa_, xa_);
       load4(pa_, xa_);
