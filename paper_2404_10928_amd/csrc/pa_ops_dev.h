@@ -1237,6 +1237,9 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     // are added afterwards, one sensor at a time with one pixel per lane, so
     // the wave never runs the FP64 delay path for all of its pixels.
     const bool near = F32 && active && is_near(P, ref, sp);
+    // a wave with near pairs of this tile to add after its loop keeps its
+    // priority a quarter longer, so that work overlaps the other waves' loops
+    const bool near_work = __ballot(near) != 0;
     SC c;
     make_sc<ND>(P, ref, sp, kl, lane * P.wpa, HB, active && !near, c);
     c.BASE += (int)(size_t)hist;  // absolute LDS byte address
@@ -1280,7 +1283,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     };
     load4(pa_, xa_);
     for (int p = p_lo; p < p_hi; p += 8) {
-      if (((p - p_lo) & 63) == 0) progress_prio(((p - p_lo) * 4) / (p_hi - p_lo));
+      if (((p - p_lo) & 63) == 0) progress_prio(((p - p_lo) * 4) / (p_hi - p_lo) - (near_work ? 1 : 0));
       load4(pb_, xb_);
       scatter4(pa_, xa_);
       load4(pa_, xa_);
