@@ -38,9 +38,12 @@ __global__ void __launch_bounds__(kBlock) fp_kernel(OpParams P, const T* __restr
   fp_body<T, PH, ND, FRAC, FIX>(P, blockIdx.x, blockIdx.x, x, y, part_q);
 }
 
+// Its LDS (about 39 KiB at the 512x512 workload) admits four work-groups, so
+// four waves per SIMD, per CU: telling the compiler so lets it use up to 128
+// VGPRs for the interleaved pixel chains instead of aiming at eight waves.
 template <int ND, bool FRAC, bool CG>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) fp2_kernel(OpParams P, const float* __restrict__ x, float* __restrict__ rows,
-                                                      int* __restrict__ klo_tab, CgDirArgs cg) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+fp2_kernel(OpParams P, const float* __restrict__ x, float* __restrict__ rows, int* __restrict__ klo_tab, CgDirArgs cg) {
   fp2_body<ND, FRAC, CG>(P, xcd_remap(blockIdx.x, gridDim.x), x, rows, klo_tab, cg);
 }
 
