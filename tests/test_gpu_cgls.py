@@ -273,3 +273,39 @@ def test_zero_iterations_and_no_sensors(pa):
     x0 = rng.uniform(size=g.image_shape)
     x, h, stop = gpu_cgls(pa, g0, np.zeros((0, 100)), 3, 0.5, np.float64, x0=x0)
     assert np.max(np.abs(x)) <= 1e-12
+
+
+PARTIAL_ROWS = {"fwd_mode": 3, "fwd_tile": (2, 2, 1)}
+
+
+@pytest.mark.parametrize("iters", [0, 1, 4])
+def test_fused_direction_under_partial_rows(pa, iters):
+    """Under the partial-row forward an FP32 solve forms p_k = s_k + beta p_{k-1}
+    inside pass 1 of q = A p_k and takes its last history row from the
+    direction kernel alone.  From a warm start, with zero iterations (only that
+    last row), one, and a few, the iterate and history follow the oracle; the
+    unfused FP32 solve (fixed-point tile rows) agrees to the same bar."""
+    g = ring_geom(n=(40, 36), S=40, K=260)
+    rng = np.random.default_rng(31)
+    y32, y64 = rounded(rng.normal(size=g.data_shape), np.float32)
+    x0g, x064 = rounded(rng.uniform(size=g.image_shape), np.float32)
+    lam = 1e-2
+    x_ref, h_ref, _ = oracle.cgls(g, y64, iters, lam, x0=x064)
+    pa.tuning_set(g, PARTIAL_ROWS, torch.float32)
+    try:
+        x, h, stop = gpu_cgls(pa, g, y32, iters, lam, np.float32, x0=x0g)
+        x_e, h_e, _ = gpu_cgls(pa, g, y32, iters, lam, np.float32, graph=False, x0=x0g)
+    finally:
+        pa.tuning_clear()
+    x_u, h_u, _ = gpu_cgls(pa, g, y32, iters, lam, np.float32, x0=x0g)
+    e = rel_l2(x, x_ref)
+    err = rel_hist(h, h_ref)
+    print(f"fused, {iters} iterations: iterate {e:.2e}, history {err.max():.2e}, "
+          f"vs unfused {rel_l2(x, x_u):.2e}")
+    assert stop == -1 and h.shape == (iters + 1, 3)
+    if iters == 0:
+        assert np.array_equal(x, x064)
+    assert e <= 1e-4 and err.max() <= 1e-4
+    assert rel_l2(x, x_u) <= 1e-4 and rel_hist(h, h_u).max() <= 1e-4
+    np.testing.assert_array_equal(x_e, x)   # eager and graph launches repeat bit for bit
+    np.testing.assert_array_equal(h_e, h)
