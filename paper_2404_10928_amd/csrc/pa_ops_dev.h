@@ -333,6 +333,23 @@ __device__ __forceinline__ T lds_load(const T* addr) {
       static_cast<unsigned>(reinterpret_cast<size_t>(addr)));
 }
 
+// Element k of a trace of n elements at base, read through a buffer resource
+// whose range is the trace: the hardware's range check returns zero for any k
+// outside 0..n-1 (a negative k is an offset beyond the range as an unsigned
+// byte offset) without touching memory, so the caller needs no index test and
+// no clamped address.  n * sizeof(T) < 2^31 (the planner caps traces at 2^22
+// samples); n = 0 reads zeros.
+template <typename T>
+__device__ __forceinline__ T trace_load(const T* base, int n, int k) {
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, n * (int)sizeof(T), 0x00020000);
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, k * 4, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, k * 8, 0, 0));
+  }
+}
+
 // Non-finite test on a value's bits.  The operator kernels are built without
 // NaN semantics, so a floating-point test, or a bit test the compiler
 // recognises as one, may be folded away for a value it takes to be finite;
@@ -498,31 +515,28 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
     }
     __syncthreads();
     // Stage the windows: wave w copies rows w, w+4, ... (row parameters are
-    // wave-uniform), 64 samples of a row per step, with the loads of eight
-    // rows in flight before their stores (every load is issued, from the
-    // first sample of the data where the row has none, and the unused ones
-    // dropped).
+    // wave-uniform, held in scalar registers), 64 samples of a row per step,
+    // with the loads of eight rows in flight before their stores.  Each row
+    // reads its sensor's trace through a buffer resource: samples outside
+    // 0..K-1 and rows beyond the chunk (an empty range) read as zero.
     constexpr int RB = 8;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     for (int i0 = 0; i0 < P.wp; i0 += 64) {
       const int i = i0 + lane;
-      for (int j0 = wave; j0 < nsc; j0 += 4 * RB) {
+      for (int j0 = wv; j0 < nsc; j0 += 4 * RB) {
         T v[RB];
-        unsigned okb = 0;
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
           const int j = j0 + 4 * u;
           const int jj = j < nsc ? j : 0;
           const int kl = __builtin_amdgcn_readfirstlane(klo_s[jj]);
           const int sj = __builtin_amdgcn_readfirstlane(sid[jj]);
-          const int k = kl + i;
-          const bool ok = j < nsc && i < P.wp && k >= 0 && k < P.K;
-          okb |= ok ? 1u << u : 0u;
-          v[u] = P.K > 0 ? y[ok ? (size_t)sj * P.K + k : 0] : (T)0;   // (no trace at all: nothing to read)
+          v[u] = trace_load(y + (size_t)sj * P.K, j < nsc ? P.K : 0, kl + i);
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
           const int j = j0 + 4 * u;
-          if (j < nsc && i < P.wp) win[j * P.wp + i] = (okb >> u) & 1u ? v[u] : (T)0;
+          if (j < nsc && i < P.wp) win[j * P.wp + i] = v[u];
         }
       }
     }
