@@ -1394,7 +1394,7 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int s = blk / P.nseg;
+  const int s = __builtin_amdgcn_readfirstlane(blk / P.nseg);   // (uniform: keeps the row addresses scalar)
   const int seg = blk - s * P.nseg;
   const int k0 = seg * P.kseg;
   const int kn = min(P.kseg, P.K - k0);
@@ -1439,11 +1439,11 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
       };
       advance();
       while (c < 4) {
-        // every lane loads (its own sample of the row, else the row's first
-        // sample), so the loads go out back to back; the unused values are
-        // dropped when they are added
+        // every lane loads its sample of the row through a buffer resource
+        // over the row, which reads zero for samples outside it, so the
+        // loads go out back to back with no test (lanes past the segment's
+        // end read what they read; their sums are never written)
         float v[kGatherLoads];
-        unsigned okm = 0;
 #pragma unroll
         for (int u = 0; u < kGatherLoads; ++u) {
           v[u] = 0.f;
@@ -1451,15 +1451,12 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
             const int b = __builtin_ctzll(m[0]);
             m[0] &= m[0] - 1;
             const int klb = __builtin_amdgcn_readlane(kl[0], b);
-            const int j = k - klb;
-            const bool ok = k_ok && j >= 0 && j < P.wpa;
-            okm |= ok ? 1u << u : 0u;
-            v[u] = srow[(size_t)(g0 + 64 * c + b) * P.wpa + (ok ? j : 0)];
+            v[u] = trace_load(srow + (size_t)(g0 + 64 * c + b) * P.wpa, P.wpa, k - klb);
             advance();
           }
         }
 #pragma unroll
-        for (int u = 0; u < kGatherLoads; ++u) acc += (okm >> u) & 1u ? (double)v[u] : 0.0;
+        for (int u = 0; u < kGatherLoads; ++u) acc += (double)v[u];
       }
     }
   }
