@@ -37,23 +37,21 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // units) and an integer reference kr = round(|D|).  For a pixel at offset o
 // from the tile centre,
 //   num = R^2 - kr^2 = (|D|^2 - kr^2) + 2 D.o + |o|^2
-// is formed in FP32 from small terms, and R - kr follows from one Newton step
-// on d (d + 2 kr) = num starting at the FP32 estimate R^2 * rsq(R^2) - kr.
-// The result is accurate to ~1e-6 samples.  The pixel enters through its
-// offset u in pixel pitches (o = hs u; half-integers, exact in FP32), so its
-// constants are the same for every plan: 2 D.o = u.(2 hs D) and
-// |o|^2 = hs^2 |u|^2.
+// is formed in FP32 from small terms (as num / 2, every term halved, which
+// is exact), and R - kr follows from one Newton step on d (d + 2 kr) = num
+// starting at the FP32 estimate R^2 * rsq(R^2) - kr.  The result is accurate
+// to ~1e-6 samples.  The pixel enters through its offset u in pixel pitches
+// (o = hs u; half-integers, exact in FP32), so its constants are the same
+// for every plan: D.o = u.(hs D) and |o|^2 / 2 = (hs^2 / 2) |u|^2.
 struct SC32 {
-  float E;      // |D|^2 - kr^2
-  float DXH, DYH, DZH;  // 2 hs D
+  float E;      // (|D|^2 - kr^2) / 2
+  float DXH, DYH, DZH;  // hs D
   float KRN;    // -kr
-  float KR2N;   // -2 kr
   float KR2;    // kr^2
-  float CMIN;   // rmin^2 - kr^2: the distance clamp in num units (never reached by far pairs)
+  float CMIN;   // (rmin^2 - kr^2) / 2: the distance clamp in num / 2 units (never reached by far pairs)
   int BASE;     // byte offset of sample (kr - t0i) in this sensor's LDS row
   int act;      // 0: sensor contributes nothing to this tile
-  float HALF;   // 0.5 (active) or 0 (inactive): weight multiplier
-  int pad;
+  int pad[3];
 };
 static_assert(sizeof(SC32) == 48, "SC32 layout");
 
@@ -176,22 +174,24 @@ __device__ __forceinline__ void make_sc(const OpParams& P, const double ref[3], 
   double dx = ref[0] - sp[0], dy = ref[1] - sp[1], dz = ND == 3 ? ref[2] - sp[2] : 0.0;
   double ra2 = dx * dx + dy * dy + dz * dz;
   double kr = rint(sqrt(ra2));
-  if (!active) {  // benign constants: num = |o|^2 + 1 >= 1, a delay of at most |o| + 1, zero weight
-    c.E = 1.f; c.DXH = 0.f; c.DYH = 0.f; c.DZH = 0.f; c.KRN = 0.f; c.KR2N = 0.f; c.KR2 = 0.f;
-    c.CMIN = 1.f; c.BASE = row_elems * esz; c.act = 0; c.HALF = 0.f;
+  // Benign constants: num = |o|^2 + 1 >= 1, a delay of at most |o| + 1 and a
+  // finite weight; the caller zeroes the contribution (the adjoint stages a
+  // zero row for the sensor, the partial-row forward gives the pair a zero
+  // fixed-point scale).
+  if (!active) {
+    c.E = 0.5f; c.DXH = 0.f; c.DYH = 0.f; c.DZH = 0.f; c.KRN = 0.f; c.KR2 = 0.f;
+    c.CMIN = 0.5f; c.BASE = row_elems * esz; c.act = 0;
     return;
   }
-  c.E = (float)(ra2 - kr * kr);
-  c.DXH = (float)(2.0 * P.hs * dx);
-  c.DYH = (float)(2.0 * P.hs * dy);
-  c.DZH = (float)(2.0 * P.hs * dz);
+  c.E = (float)(0.5 * (ra2 - kr * kr));
+  c.DXH = (float)(P.hs * dx);
+  c.DYH = (float)(P.hs * dy);
+  c.DZH = (float)(P.hs * dz);
   c.KRN = (float)(-kr);
-  c.KR2N = (float)(-2.0 * kr);
   c.KR2 = (float)(kr * kr);
-  c.CMIN = (float)(P.rmin * P.rmin - kr * kr);
+  c.CMIN = (float)(0.5 * (P.rmin * P.rmin - kr * kr));
   c.BASE = ((int)kr - P.t0i - klo + row_elems) * esz;
   c.act = 1;
-  c.HALF = 0.5f;
 }
 
 template <int ND>
@@ -220,42 +220,41 @@ struct Near32 {
 static_assert(sizeof(Near32) == 32, "Near32 layout");
 
 // The per-pair arithmetic.  Returns the LDS byte address of tap k0 (rows of
-// ESZ-byte elements), the fraction f and the tap weight in kernel units
-// (FP32: 1 / (2R); FP64: 1 / R).  Far pairs never reach the distance clamp
-// (the near radius covers r_min), so CLAMP only chooses whether the max
-// instruction is emitted: both choices give the same taps, and the kernels
-// use whichever schedules better (measured: A without, A^T with).
+// ESZ-byte elements), the fraction f and the tap weight 1 / R.  Far pairs
+// never reach the distance clamp (the near radius covers r_min), so CLAMP
+// only chooses whether the max instruction is emitted: both choices give the
+// same taps, and the kernels use whichever schedules better (measured: A
+// without, A^T with).  hs2h = hs^2 / 2.
 template <int ND, bool FRAC, int ESZ, bool CLAMP, typename C>
-__device__ __forceinline__ void phase32(const C& c, float cmin, float half, const Pix32& px, float t0f, float hs2,
-                                        int& kbyte, float& f, float& wt) {
-  float t = fmaf(px.uq, hs2, c.E);
-  float num = fmaf(px.uy, c.DYH, t);
-  if (ND == 3) num = fmaf(px.uz, c.DZH, num);
-  num = fmaf(px.ux, c.DXH, num);
-  if (CLAMP) num = fmaxf(num, cmin);
-  const float R2 = num + c.KR2;
-  const float w = __builtin_amdgcn_rsqf(R2);
+__device__ __forceinline__ void phase32(const C& c, float cmin, const Pix32& px, float t0f, float hs2h,
+                                        int& kbyte, float& f, float& w) {
+  float t = fmaf(px.uq, hs2h, c.E);
+  float nh = fmaf(px.uy, c.DYH, t);          // num / 2
+  if (ND == 3) nh = fmaf(px.uz, c.DZH, nh);
+  nh = fmaf(px.ux, c.DXH, nh);
+  if (CLAMP) nh = fmaxf(nh, cmin);
+  const float R2 = fmaf(2.0f, nh, c.KR2);    // num + kr^2 (the doubling is exact)
+  w = __builtin_amdgcn_rsqf(R2);             // 1 / R
   const float da = fmaf(R2, w, c.KRN);       // R - kr, FP32 estimate
-  const float r1 = fmaf(c.KR2N, da, num);
-  const float r = fmaf(-da, da, r1);         // num - da (da + 2 kr)
-  wt = half * w;                             // 1 / (2R)
-  float d = fmaf(r, wt, da);                 // Newton-corrected R - kr
+  const float h = fmaf(-0.5f, da, c.KRN);    // -(kr + da / 2)
+  const float rh = fmaf(da, h, nh);          // (num - da (da + 2 kr)) / 2 = (R^2 - (kr + da)^2) / 2
+  float d = fmaf(rh, w, da);                 // Newton-corrected R - kr
   if (FRAC) d = d - t0f;
   f = __builtin_amdgcn_fractf(d);           // d - floor(d), exact
   kbyte = (int)floorf(d) * ESZ + c.BASE;
 }
 
 template <int ND, bool FRAC, int ESZ, bool CLAMP = true>
-__device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, float hs2, int& kbyte, float& f,
-                                      float& wt) {
-  phase32<ND, FRAC, ESZ, CLAMP>(c, c.CMIN, c.HALF, px, t0f, hs2, kbyte, f, wt);
+__device__ __forceinline__ void phase(const SC32& c, const Pix32& px, float t0f, float hs2h, int& kbyte, float& f,
+                                      float& w) {
+  phase32<ND, FRAC, ESZ, CLAMP>(c, c.CMIN, px, t0f, hs2h, kbyte, f, w);
 }
 
-// Forward operator: far pairs only (active, no clamp reached), weight 1 / (2R).
+// Forward operator: far pairs only (active, no clamp reached).
 template <int ND, bool FRAC, int ESZ, bool CLAMP = false>
-__device__ __forceinline__ void phase(const FpSC32& c, const Pix32& px, float t0f, float hs2, int& kbyte, float& f,
-                                      float& wt) {
-  phase32<ND, FRAC, ESZ, false>(c, 0.f, 0.5f, px, t0f, hs2, kbyte, f, wt);
+__device__ __forceinline__ void phase(const FpSC32& c, const Pix32& px, float t0f, float hs2h, int& kbyte, float& f,
+                                      float& w) {
+  phase32<ND, FRAC, ESZ, false>(c, 0.f, px, t0f, hs2h, kbyte, f, w);
 }
 
 __device__ __forceinline__ FpSC32 fp_sc(const SC32& c) {
@@ -265,7 +264,6 @@ __device__ __forceinline__ FpSC32 fp_sc(const SC32& c) {
   o.DYH = c.DYH;
   o.DZH = c.DZH;
   o.KRN = c.KRN;
-  o.KR2N = c.KR2N;
   o.KR2 = c.KR2;
   o.BASE = c.BASE;
   return o;
@@ -541,8 +539,8 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
       }
     }
     __syncthreads();
-    // Sensors whose arrivals miss the trace carry zero weight and a bounded
-    // delay into a zero row, so the loop needs no per-sensor test.
+    // Sensors whose arrivals miss the trace carry a finite weight and a
+    // bounded delay into a zero row, so the loop needs no per-sensor test.
     // Four sensors per step: four delays, then four independent window
     // reads, then the sums in sensor order (the order never changes).
     int j = 0;
@@ -551,7 +549,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
       PH f[4], wt[4];
       T y0[4], y1[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) phase<ND, FRAC, (int)sizeof(T)>(sct[j + u], px, t0f, P.hs2f, kb[u], f[u], wt[u]);
+      for (int u = 0; u < 4; ++u) phase<ND, FRAC, (int)sizeof(T)>(sct[j + u], px, t0f, P.hs2h, kb[u], f[u], wt[u]);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb[u]));
@@ -564,7 +562,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
     for (; j < nfar; ++j) {
       int kb;
       PH f, wt;
-      phase<ND, FRAC, (int)sizeof(T)>(sct[j], px, t0f, P.hs2f, kb, f, wt);
+      phase<ND, FRAC, (int)sizeof(T)>(sct[j], px, t0f, P.hs2h, kb, f, wt);
       const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
       const T y0 = lds_load(tap);
       const T y1 = lds_load(tap + 1);
@@ -578,7 +576,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
           const SC32& c = sct[j];
           int kb;
           float f, wt;
-          phase_near<ND, FRAC, (int)sizeof(T)>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, c.HALF, kb, f, wt);
+          phase_near<ND, FRAC, (int)sizeof(T)>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, 1.0f, kb, f, wt);
           const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
           const T y0 = lds_load(tap);
           const T y1 = lds_load(tap + 1);
@@ -590,7 +588,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
   }
 
   const size_t idx = ((size_t)iz * P.ny + iy) * P.nx + ix;
-  const T scale = F32 ? (sizeof(T) == 4 ? (T)P.out_scale : (T)P.out_scale_h) : (T)P.out_scale_d;
+  const T scale = (T)P.out_scale;   // (sums of w y)
   if (!CG) {
     if (valid) out[idx] = acc * scale;
     return;
@@ -872,8 +870,13 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
           b *= sx;
           post = ldexp(1.0, -e);
         }
+        // the bound is of taps w x / 2: the fixed point takes 2^30 / b times
+        // that, so w x is scaled by half of it and each integer read back
+        // at twice 1 / scale
         scl = 1073741824.0f * __builtin_amdgcn_rcpf(b);
         inv = post / (double)scl;
+        scl *= 0.5f;
+        inv *= 2.0;
       }
 #pragma unroll
       for (int u = 0; u < G; ++u) {
@@ -887,7 +890,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
             int kb;
             PH f, wt;
             if constexpr (FIX) {
-              phase<ND, FRAC, HB, false>(c, px[q], t0f, P.hs2f, kb, f, wt);
+              phase<ND, FRAC, HB, false>(c, px[q], t0f, P.hs2h, kb, f, wt);
               const float vs = (wt * (float)xv[u][q]) * scl;
               const int it = round_i(vs);
               const int i1 = round_i(vs * f);
@@ -895,7 +898,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
               lds_add(bin, it - i1);
               lds_add(bin + 1, i1);
             } else {
-              phase<ND, FRAC, HB, false>(c, px[q], t0f, P.hs2f, kb, f, wt);
+              phase<ND, FRAC, HB, false>(c, px[q], t0f, P.hs2h, kb, f, wt);
               const double v = (double)wt * (double)xv[u][q];
               const double a1 = v * (double)f;
               double* bin = reinterpret_cast<double*>(static_cast<size_t>(kb));
@@ -922,7 +925,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
             pix_offsets<ND>(P, p % TX, (p / TX) % TY, p / (TX * TY), o);
             int kb;
             float f, wt;
-            phase_near<ND, FRAC, HB>(nn, o, rmin2, P.t0fd, c.BASE, 0.5f, kb, f, wt);
+            phase_near<ND, FRAC, HB>(nn, o, rmin2, P.t0fd, c.BASE, 1.0f, kb, f, wt);
             if constexpr (FIX) {
               const float vs = (wt * (float)xv[u][q]) * scl;
               const int it = round_i(vs);
@@ -961,7 +964,7 @@ __device__ __forceinline__ void fp_body(const OpParams& P, int b, int pidx, cons
 
   // ---- the segment out: the four waves' histograms in a fixed order
   const double* h0 = reinterpret_cast<const double*>(smem + L.hist);
-  const double scale = P32 ? P.out_scale_h : P.out_scale_d;
+  const double scale = P.out_scale;   // (sums of w x)
   const int kn = min(P.fseg, P.K - k0);
   double qq = 0.0;
   for (int i = tid; i < kn; i += kBlock) {
@@ -1247,7 +1250,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     if (nlx <= 0 || nly <= 0 || nlz <= 0) continue;
     double ref[3];
     tile_ref<ND>(P, bx, by, bz, ref);
-    // Near (tile, sensor) pairs take benign zero-weight constants here and
+    // Near (tile, sensor) pairs take benign constants and a zero scale here and
     // are added afterwards, one sensor at a time with one pixel per lane, so
     // the wave never runs the FP64 delay path for all of its pixels.
     const bool near = F32 && active && is_near(P, ref, sp);
@@ -1257,6 +1260,9 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     SC c;
     make_sc<ND>(P, ref, sp, kl, lane * P.wpa, HB, active && !near, c);
     c.BASE += (int)(size_t)hist;  // absolute LDS byte address
+    // w x times half the fixed-point scale (the bound is of taps w x / 2,
+    // and the rows hold sums of w x / 2); near and inactive pairs add zeros here
+    const float scl_m = active && !near ? 0.5f * scl : 0.f;
     asm volatile("" : "+v"(c.BASE));  // keep "k * HB + BASE" a single shift-add
     const T* xm = xs + m * kBlock;
     // Every pixel of the base tile, in order, four per step.  Pixels beyond
@@ -1270,7 +1276,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
     const int p_lo = part * (NPIX / parts);
     const int p_hi = p_lo + NPIX / parts;
     const PX* ptab = pix_table<ND>();
-    float hs2v = P.hs2f;
+    float hs2v = P.hs2h;
     asm volatile("" : "+v"(hs2v));  // a VGPR operand: the pixel's uq is the FMA's one scalar operand
     int po = p_lo;
     PX pa_[4], pb_[4];
@@ -1289,7 +1295,7 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
         T f, wt;
         phase<ND, FRAC, HB, false>(c, pp[j], t0f, hs2v, kb, f, wt);
         H* bin = reinterpret_cast<H*>(static_cast<size_t>(kb));
-        const float vs = (wt * xv[j]) * scl;   // (wt = 1 / (2R) also corrects the delay: not pre-scaled)
+        const float vs = (wt * xv[j]) * scl_m;
         const int i1 = round_i(vs * f);
         lds_add(bin, round_i(vs) - i1);
         lds_add(bin + 1, i1);
@@ -1460,7 +1466,7 @@ __device__ __forceinline__ void gather_body(const OpParams& P, int blk, int pidx
       }
     }
   }
-  const double scale = 2.0 * P.inv_cdt;
+  const double scale = 2.0 * P.out_scale;   // (the rows hold sums of w x / 2)
   double q = 0.0;
   if (k_ok) {
     const T out = (T)(acc * scale);

@@ -155,7 +155,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
   op.S = g->n_sensors;
   op.K = g->n_samples;
   op.hs = hs;
-  op.hs2f = (float)(hs * hs);
+  op.hs2h = (float)(0.5 * hs * hs);
   op.inv_cdt = inv_cdt;
   op.rmin = (g->r_min > 0 ? g->r_min : 0.5 * g->h) * inv_cdt;
   const double t0i = std::floor(T0);
@@ -303,9 +303,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     }
   }
 
-  op.out_scale = (float)(2.0 * inv_cdt);   // FP32 phase accumulates w / 2
-  op.out_scale_h = 2.0 * inv_cdt;
-  op.out_scale_d = inv_cdt;                // FP64 phase accumulates w
+  op.out_scale = inv_cdt;
   // The adjoint runs whenever there are pixels (with no sensors or samples it
   // writes zeros, and its CGLS epilogue still has work); the forward
   // operator whenever there are samples to write (with no pixels its

@@ -49,7 +49,7 @@ struct OpParams {
   int32_t S, K;             // sensors, samples
   double org[3];            // position of pixel (0,0,0), sample units
   double hs;                // pixel pitch, sample units
-  float hs2f;               // hs^2 in FP32 (the FP32 phase's |o|^2 = hs^2 |u|^2 term)
+  float hs2h;               // hs^2 / 2 in FP32 (the FP32 phase's |o|^2 / 2 = (hs^2 / 2) |u|^2 term)
   double rmin;              // distance clamp, sample units
   double inv_cdt;           // metres -> sample units
   int32_t t0i;              // floor(t0 / dt)
@@ -77,9 +77,7 @@ struct OpParams {
   int32_t nseg;             // pass 2: segments per trace
   double near_r2;           // squared tile-centre distance (sample units) below which a
                             // sensor takes the FP64 delay path in the FP32-phase kernels
-  float out_scale;          // converts accumulated kernel units to 1/metres (FP32 phase, float data)
-  double out_scale_h;       // same in FP64 (FP32 phase accumulates w / 2)
-  double out_scale_d;       // FP64 phase (accumulates w)
+  double out_scale;         // converts sums of tap weights w = 1 / R to 1/metres
 };
 
 // LDS layouts, shared by the planner (sizes) and the kernels (offsets).
@@ -115,8 +113,9 @@ constexpr int32_t kFpNear = 1 << 24;
 // arithmetic: the far-pair fields of the adjoint's constants (the same values
 // for the same tile and sensor).
 struct FpSC32 {
-  float E, DXH, DYH, DZH, KRN, KR2N, KR2;
+  float E, DXH, DYH, DZH, KRN, KR2;
   int32_t BASE;
+  int32_t pad;
 };
 
 constexpr int kFwdGroupMax = 8;  // forward: list entries a wave processes together (one fixed-point scale):
