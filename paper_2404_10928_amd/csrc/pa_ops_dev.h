@@ -220,11 +220,10 @@ struct Near32 {
 static_assert(sizeof(Near32) == 32, "Near32 layout");
 
 // The per-pair arithmetic.  Returns the LDS byte address of tap k0 (rows of
-// ESZ-byte elements), the fraction f and the tap weight 1 / R.  Far pairs
-// never reach the distance clamp (the near radius covers r_min), so CLAMP
-// only chooses whether the max instruction is emitted: both choices give the
-// same taps, and the kernels use whichever schedules better (measured: A
-// without, A^T with).  hs2h = hs^2 / 2.
+// ESZ-byte entries), the fraction f and the tap weight 1 / R.  Far pairs
+// never reach the distance clamp (the near radius covers r_min), and
+// inactive ones have num >= 1, so the FP32 kernels leave the max instruction
+// out (CLAMP = false): either choice gives the same taps.  hs2h = hs^2 / 2.
 template <int ND, bool FRAC, int ESZ, bool CLAMP, typename C>
 __device__ __forceinline__ void phase32(const C& c, float cmin, const Pix32& px, float t0f, float hs2h,
                                         int& kbyte, float& f, float& w) {
@@ -433,12 +432,16 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
   constexpr int TX = Tile<ND>::X, TY = Tile<ND>::Y, TZ = Tile<ND>::Z;
   constexpr bool F32 = sizeof(PH) == 4;  // FP32 delay arithmetic (with the FP64 near path)
   extern __shared__ __align__(16) unsigned char smem[];
-  const BpLayout L = bp_layout(P.sc, P.wp, sizeof(T), sizeof(SC), near_bytes<PH>());
+  // window entries are (y_k, y_{k+1} - y_k) pairs: one LDS read gives a
+  // pair's two taps' interpolation operands
+  using T2 = T __attribute__((ext_vector_type(2)));
+  constexpr int ESZ = (int)sizeof(T2);
+  const BpLayout L = bp_layout(P.sc, P.wp, sizeof(T2), sizeof(SC), near_bytes<PH>());
   SC* sct = reinterpret_cast<SC*>(smem + L.sct);
   int* klo_s = reinterpret_cast<int*>(smem + L.klo);
   int* sid = reinterpret_cast<int*>(smem + L.sid);
   Near32* ntab = reinterpret_cast<Near32*>(smem + L.nd);
-  T* win = reinterpret_cast<T*>(smem + L.win);
+  T2* win = reinterpret_cast<T2*>(smem + L.win);
   __shared__ double red[4];
   __shared__ int cnt[8];
 
@@ -497,7 +500,7 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
     if (mine) {
       const int pos = near ? nfar + near_before + __popcll(bnear & lt_mask) : far_before + __popcll(bfar & lt_mask);
       SC c;
-      make_sc<ND>(P, ref, sp, kl, pos * P.wp, (int)sizeof(T), in_trace, c);
+      make_sc<ND>(P, ref, sp, kl, pos * P.wp, ESZ, in_trace, c);
       c.BASE += (int)(size_t)win;  // absolute LDS byte address of the row's reference sample
       sct[pos] = c;
       klo_s[pos] = in_trace ? kl : P.K + 8;  // inactive rows stage zeros
@@ -513,60 +516,66 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
     }
     __syncthreads();
     // Stage the windows: wave w copies rows w, w+4, ... (row parameters are
-    // wave-uniform, held in scalar registers), 64 samples of a row per step,
+    // wave-uniform, held in scalar registers), 64 entries of a row per step,
     // with the loads of eight rows in flight before their stores.  Each row
     // reads its sensor's trace through a buffer resource: samples outside
-    // 0..K-1 and rows beyond the chunk (an empty range) read as zero.
+    // 0..K-1 and rows beyond the chunk (an empty range) read as zero.  Entry
+    // i holds sample k = klo + i and the difference to sample k + 1.
     constexpr int RB = 8;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     for (int i0 = 0; i0 < P.wp; i0 += 64) {
       const int i = i0 + lane;
       for (int j0 = wv; j0 < nsc; j0 += 4 * RB) {
-        T v[RB];
+        T v0[RB], v1[RB];
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
           const int j = j0 + 4 * u;
           const int jj = j < nsc ? j : 0;
           const int kl = __builtin_amdgcn_readfirstlane(klo_s[jj]);
           const int sj = __builtin_amdgcn_readfirstlane(sid[jj]);
-          v[u] = trace_load(y + (size_t)sj * P.K, j < nsc ? P.K : 0, kl + i);
+          const T* tr = y + (size_t)sj * P.K;
+          const int n = j < nsc ? P.K : 0;
+          v0[u] = trace_load(tr, n, kl + i);
+          v1[u] = trace_load(tr, n, kl + i + 1);
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
           const int j = j0 + 4 * u;
-          if (j < nsc && i < P.wp) win[j * P.wp + i] = v[u];
+          if (j < nsc && i < P.wp) {
+            T2 e;
+            e.x = v0[u];
+            e.y = v1[u] - v0[u];
+            win[j * P.wp + i] = e;
+          }
         }
       }
     }
     __syncthreads();
     // Sensors whose arrivals miss the trace carry a finite weight and a
     // bounded delay into a zero row, so the loop needs no per-sensor test.
+    // Only the FP64-delay kernels, where every sensor takes this loop, can
+    // reach the distance clamp.
+    constexpr bool CLAMP = !F32;
     // Four sensors per step: four delays, then four independent window
     // reads, then the sums in sensor order (the order never changes).
     int j = 0;
     for (; j + 4 <= nfar; j += 4) {
       int kb[4];
-      PH f[4], wt[4];
-      T y0[4], y1[4];
+      PH f[4], w[4];
+      T2 e[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) phase<ND, FRAC, (int)sizeof(T)>(sct[j + u], px, t0f, P.hs2h, kb[u], f[u], wt[u]);
+      for (int u = 0; u < 4; ++u) phase<ND, FRAC, ESZ, CLAMP>(sct[j + u], px, t0f, P.hs2h, kb[u], f[u], w[u]);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb[u]));
-        y0[u] = lds_load(tap);
-        y1[u] = lds_load(tap + 1);
-      }
+      for (int u = 0; u < 4; ++u) e[u] = lds_load(reinterpret_cast<const T2*>(static_cast<size_t>(kb[u])));
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = fma((T)wt[u], fma((T)f[u], y1[u] - y0[u], y0[u]), acc);
+      for (int u = 0; u < 4; ++u) acc = fma((T)w[u], fma((T)f[u], e[u].y, e[u].x), acc);
     }
     for (; j < nfar; ++j) {
       int kb;
-      PH f, wt;
-      phase<ND, FRAC, (int)sizeof(T)>(sct[j], px, t0f, P.hs2h, kb, f, wt);
-      const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
-      const T y0 = lds_load(tap);
-      const T y1 = lds_load(tap + 1);
-      acc = fma((T)wt, fma((T)f, y1 - y0, y0), acc);
+      PH f, w;
+      phase<ND, FRAC, ESZ, CLAMP>(sct[j], px, t0f, P.hs2h, kb, f, w);
+      const T2 e = lds_load(reinterpret_cast<const T2*>(static_cast<size_t>(kb)));
+      acc = fma((T)w, fma((T)f, e.y, e.x), acc);
     }
     if constexpr (F32) {
       if (nfar < nsc) {
@@ -575,12 +584,10 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
         for (; j < nsc; ++j) {
           const SC32& c = sct[j];
           int kb;
-          float f, wt;
-          phase_near<ND, FRAC, (int)sizeof(T)>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, 1.0f, kb, f, wt);
-          const T* tap = reinterpret_cast<const T*>(static_cast<size_t>(kb));
-          const T y0 = lds_load(tap);
-          const T y1 = lds_load(tap + 1);
-          acc = fma((T)wt, fma((T)f, y1 - y0, y0), acc);
+          float f, w;
+          phase_near<ND, FRAC, ESZ>(ntab[j], o, P.rmin * P.rmin, P.t0fd, c.BASE, 1.0f, kb, f, w);
+          const T2 e = lds_load(reinterpret_cast<const T2*>(static_cast<size_t>(kb)));
+          acc = fma((T)w, fma((T)f, e.y, e.x), acc);
         }
       }
     }

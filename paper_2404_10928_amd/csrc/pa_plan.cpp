@@ -210,7 +210,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     double diag = std::sqrt(ex * ex + ey * ey + ez * ez);
     if (diag > 1e6) return fail(msg, PA_ERR_UNSUPPORTED, "pixel pitch spans too many samples");
     op.wp = (int32_t)std::ceil(diag) + 5;
-    const size_t per = sc_bytes + 8 + near_bytes + (size_t)op.wp * elem;
+    const size_t per = sc_bytes + 8 + near_bytes + (size_t)op.wp * 2 * elem;   // window entries: sample pairs
     const size_t slack = 64;  // alignment of the four LDS arrays
     const size_t budget = tuned.adj_lds > 0 ? std::min<size_t>((size_t)tuned.adj_lds, kLdsMax) : 40 * 1024;
     int64_t sc_max = budget > slack ? (int64_t)((budget - slack) / per) : 0;
@@ -221,7 +221,7 @@ pa_status make_plan(const pa_geometry* g, pa_dtype dtype, Plan* plan, std::strin
     int64_t S = std::max<int64_t>(g->n_sensors, 1);
     int64_t nchunk = (S + sc_max - 1) / sc_max;
     op.sc = (int32_t)((S + nchunk - 1) / nchunk);
-    pl.bp_lds = bp_layout(op.sc, op.wp, elem, sc_bytes, near_bytes).total;
+    pl.bp_lds = bp_layout(op.sc, op.wp, 2 * elem, sc_bytes, near_bytes).total;
     if (pl.bp_lds > kLdsMax) return fail(msg, PA_ERR_UNSUPPORTED, "adjoint LDS plan exceeds 160 KiB");
   }
 

@@ -84,7 +84,8 @@ struct OpParams {
 struct BpLayout {
   size_t sct, klo, sid, nd, win, total;
 };
-// sc sensors per chunk, wp samples per window row, elem bytes per sample;
+// sc sensors per chunk, wp entries per window row, elem bytes per entry (a
+// sample and its difference to the next);
 // sc_bytes per-sensor constants; near_bytes per-sensor FP64 table (0 in FP64 kernels).
 PA_HD inline BpLayout bp_layout(int sc, int wp, size_t elem, size_t sc_bytes, size_t near_bytes) {
   BpLayout L;
