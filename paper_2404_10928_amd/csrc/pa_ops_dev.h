@@ -347,6 +347,16 @@ __device__ __forceinline__ T trace_load(const T* base, int n, int k) {
   }
 }
 
+// Stores v as element k of a row of n elements at base, through a buffer
+// resource whose range is the row: the hardware's range check drops stores
+// with k outside 0..n-1, so the caller needs no lane test.
+template <typename T>
+__device__ __forceinline__ void row_store(T* base, int n, int k, T v) {
+  static_assert(sizeof(T) == 4, "32-bit elements");
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, n * 4, 0x00020000);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, k * 4, 0, 0);
+}
+
 // Non-finite test on a value's bits.  The operator kernels are built without
 // NaN semantics, so a floating-point test, or a bit test the compiler
 // recognises as one, may be folded away for a value it takes to be finite;
@@ -1025,8 +1035,9 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
   // chunk-major: with the XCD remap of the launch, each XCD takes a
   // contiguous run of (chunk, tile) blocks, so one chunk's rows are written
   // within two XCDs, where pass 2 (remapped the same way) reads them
-  const int chunk = b / P.n_atiles;
-  const int at = b - chunk * P.n_atiles;
+  // (b, chunk and at are uniform; saying so keeps the row addresses scalar)
+  const int chunk = __builtin_amdgcn_readfirstlane(b / P.n_atiles);
+  const int at = __builtin_amdgcn_readfirstlane(b - chunk * P.n_atiles);
   const int ax = at % P.natile[0];
   const int ay = (at / P.natile[0]) % P.natile[1];
   const int az = at / (P.natile[0] * P.natile[1]);
@@ -1357,27 +1368,31 @@ __device__ __forceinline__ void fp2_body(const OpParams& P, int b, const float* 
 
   // histogram rows out, row (sensor, forward tile) at ((s * n_atiles) + at) * wpa:
   // wave w takes rows w, w + 4, ..., 64 samples of a row per step, with the
-  // LDS reads of eight rows issued before their conversions and stores; a
-  // row's scale comes from the lane that holds it
+  // LDS reads of eight rows (and their scales) issued before their
+  // conversions and stores.  Row indices and addresses are wave-uniform;
+  // each row is stored through a buffer resource over it, which drops the
+  // lanes past its end.
   {
     constexpr int RB = 8;
-    const double inv_l = inv_a[lane];
     const int nrw = (min(NS, P.S - chunk * NS) - wave + 3) >> 2;   // this wave's rows
-    for (int i = lane; i - lane < P.wpa; i += 64) {
-      const bool iok = i < P.wpa;
+    for (int i0 = 0; i0 < P.wpa; i0 += 64) {
+      const int i = i0 + lane;
+      const int ic = i < P.wpa ? i : 0;   // (an in-row bin for the LDS read of lanes past the end)
       for (int r0 = 0; r0 < nrw; r0 += RB) {
         H hv[RB];
+        double inv[RB];
 #pragma unroll
-        for (int u = 0; u < RB; ++u)   // unconditional reads (bin 0 in place of the missing ones)
-          hv[u] = hist[iok && r0 + u < nrw ? (wave + 4 * (r0 + u)) * P.wpa + i : 0];
+        for (int u = 0; u < RB; ++u) {
+          const int jr = wave + 4 * (r0 + u < nrw ? r0 + u : 0);
+          hv[u] = hist[jr * P.wpa + ic];
+          inv[u] = inv_a[jr];
+        }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
           const int j = wave + 4 * (r0 + u);
-          if (r0 + u < nrw) {   // wave-uniform
-            const double inv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(inv_l), j),
-                                                __builtin_amdgcn_readlane(__double2loint(inv_l), j));
-            if (iok) rows[((size_t)(chunk * NS + j) * P.n_atiles + at) * P.wpa + i] = (T)((double)hv[u] * inv);
-          }
+          if (r0 + u < nrw)   // wave-uniform
+            row_store(rows + ((size_t)(chunk * NS + j) * P.n_atiles + at) * P.wpa, P.wpa, i,
+                      (T)((double)hv[u] * inv[u]));
         }
       }
     }
