@@ -545,8 +545,14 @@ __device__ __forceinline__ void bp_body(const OpParams& P, int tile, int pidx, c
           const int sj = __builtin_amdgcn_readfirstlane(sid[jj]);
           const T* tr = y + (size_t)sj * P.K;
           const int n = j < nsc ? P.K : 0;
+          // Two loads, kept apart: merged into one two-element load, the
+          // range check of a window starting before sample 0 also zeroes
+          // sample 0 at k = -1 (measured), so the compiler must not see that
+          // the second index is the first plus one.
+          int k1 = kl + i + 1;
+          asm volatile("" : "+v"(k1));
           v0[u] = trace_load(tr, n, kl + i);
-          v1[u] = trace_load(tr, n, kl + i + 1);
+          v1[u] = trace_load(tr, n, k1);
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {

@@ -240,3 +240,33 @@ def test_c5_sampled(pa):
     e_a = rel_l2(xa[pix], np.array([oracle.adjoint_at(g, y64, int(p)) for p in pix]))
     print(f"C5 sampled: forward {e_f:.3e} adjoint {e_a:.3e}")
     assert e_f <= F32_GATE and e_a <= F32_GATE
+
+
+@pytest.mark.parametrize("cut", ["late", "early"])
+def test_adjoint_reads_only_inside_each_trace(pa, cut):
+    """Aᵀ stages each sensor's trace window through a buffer resource whose
+    range is that trace, so samples before 0 and from K on read as zero.  The
+    traces sit inside a larger buffer whose other elements are NaN: a read
+    before the first trace, past the last one or across into a neighbouring
+    trace would change the image or make it NaN.  Arrivals run past the
+    trace's end ("late") or start before sample 0 ("early")."""
+    g = ring_geom(n=(48, 40), S=64, K=200)
+    if cut == "late":
+        g = g.replace(dt=g.dt * 0.6)
+    else:
+        half_diag = math.hypot(47, 39) * 1e-4 / 2
+        g = g.replace(t0=half_diag / 1500.0)
+    rng = np.random.default_rng(29)
+    y = rng.normal(size=g.data_shape)
+    pad = 4096
+    n = g.data_shape[0] * g.data_shape[1]
+    for dt, gate in ((np.float32, F32_GATE), (np.float64, F64_GATE)):
+        yg, y64 = rounded(y, dt)
+        big = torch.full((n + 2 * pad,), float("nan"), dtype=torch.float32 if dt == np.float32 else torch.float64,
+                         device="cuda")
+        big[pad:pad + n] = torch.from_numpy(np.ascontiguousarray(yg).reshape(-1)).to("cuda")
+        yv = big[pad:pad + n].view(g.data_shape)
+        xa = pa.adjoint(yv, g).cpu().numpy().astype(np.float64)
+        e = rel_l2(xa, oracle.adjoint(g, y64))
+        print(f"{cut} {np.dtype(dt).name}: adjoint {e:.3e}", flush=True)
+        assert np.all(np.isfinite(xa)) and e <= gate
