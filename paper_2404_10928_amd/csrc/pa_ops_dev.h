@@ -335,7 +335,9 @@ __device__ __forceinline__ T lds_load(const T* addr) {
 // outside 0..n-1 (a negative k is an offset beyond the range as an unsigned
 // byte offset) without touching memory, so the caller needs no index test and
 // no clamped address.  n * sizeof(T) < 2^31 (the planner caps traces at 2^22
-// samples); n = 0 reads zeros.
+// samples); n = 0 reads zeros.  Two calls at adjacent indices must not be
+// merged into one wider load: its range check returns zero for element 0
+// when the wider load starts at k = -1.
 template <typename T>
 __device__ __forceinline__ T trace_load(const T* base, int n, int k) {
   const __amdgpu_buffer_rsrc_t r =

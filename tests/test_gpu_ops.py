@@ -270,3 +270,17 @@ def test_adjoint_reads_only_inside_each_trace(pa, cut):
         e = rel_l2(xa, oracle.adjoint(g, y64))
         print(f"{cut} {np.dtype(dt).name}: adjoint {e:.3e}", flush=True)
         assert np.all(np.isfinite(xa)) and e <= gate
+    # the forward operators on the same cut traces: sensor-major, and the
+    # partial rows, whose pass 2 reads each row through a buffer resource
+    xg, x64 = rounded(rng.uniform(size=g.image_shape), np.float32)
+    y_ref = oracle.forward(g, x64)
+    for method in ("sensor-major", "partial rows"):
+        if method == "partial rows":
+            pa.tuning_set(g, {"fwd_mode": 3, "fwd_tile": (2, 2, 1)}, torch.float32)
+        try:
+            yf = run_forward(pa, g, xg, np.float32)
+        finally:
+            pa.tuning_clear()
+        e = rel_l2(yf, y_ref)
+        print(f"{cut} forward ({method}): {e:.3e}", flush=True)
+        assert e <= F32_GATE
